@@ -1,0 +1,333 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test checks the oracle against mathematics or crystallography:
+closed forms of the 12-6 potential at special distances, F = -grad E by
+central differences, W = -dE/dlambda under uniform scaling, Newton's third
+law, the FCC shell structure, lattice sums by direct enumeration of lattice
+vectors, the O(N^2) definition of the list, invariances, and energy
+conservation of velocity Verlet.  None of these runs on a GPU.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle.ljref import half_pairs_set
+from paper_1806_05713_amd import synth
+
+
+def two_atoms(r, axis=0, L=10.0, across_face=False):
+    """Two atoms a distance r apart along an axis, optionally straddling the
+    periodic face (atom 0 near L, atom 1 near 0)."""
+    pos = np.full((2, 3), L / 2.0)
+    if across_face:
+        pos[0, axis] = L - r / 2.0
+        pos[1, axis] = r / 2.0
+    else:
+        pos[0, axis] = L / 2.0 - r / 2.0
+        pos[1, axis] = L / 2.0 + r / 2.0
+    return pos, np.array([L, L, L])
+
+
+def eval_pair(oracle, r, eps, sigma, rc, axis=0, across_face=False):
+    pos, box = two_atoms(r, axis, L=max(10.0, 2.5 * rc), across_face=across_face)
+    rp = np.array([0, 1, 1], dtype=np.int64)
+    col = np.array([1], dtype=np.int32)
+    return oracle.forces(pos, box, eps, sigma, rc, rp, col)
+
+
+@pytest.mark.parametrize("eps,sigma", [(1.0, 1.0), (0.7, 1.3), (2.5, 0.8)])
+@pytest.mark.parametrize("axis", [0, 1, 2])
+@pytest.mark.parametrize("across_face", [False, True])
+def test_two_particle_closed_forms(oracle, eps, sigma, axis, across_face):
+    rc = 3.0 * sigma
+    # r = sigma: V = 0 there, dV/dr = -24 eps / sigma, so the force on j points
+    # away from i with magnitude 24 eps / sigma and r.F = 24 eps.
+    F, E_sig, W, n = eval_pair(oracle, sigma, eps, sigma, rc, axis, across_face)
+    direction = 1.0   # atom 1 sits r further along +axis than (the image of) atom 0
+    assert n == 1
+    assert F[1, axis] == pytest.approx(direction * 24.0 * eps / sigma, rel=1e-12)
+    assert F[0, axis] == pytest.approx(-direction * 24.0 * eps / sigma, rel=1e-12)
+    assert np.all(F[:, [d for d in range(3) if d != axis]] == 0.0)
+    assert W == pytest.approx(24.0 * eps, rel=1e-12)
+    # r = 2^(1/6) sigma: the minimum of the well, zero force, depth -eps.
+    rmin = 2.0 ** (1.0 / 6.0) * sigma
+    Fm, E_min, Wm, _ = eval_pair(oracle, rmin, eps, sigma, rc, axis, across_face)
+    assert np.max(np.abs(Fm)) < 1e-12 * eps / sigma
+    assert abs(Wm) < 1e-12 * eps
+    assert E_min - E_sig == pytest.approx(-eps, rel=1e-12)
+    # The shifted energy goes to zero as r -> rc from below (V(rc) = 0 after the
+    # shift), with slope |F(rc)| -- so just inside rc it is ~0.
+    F_in, E_in, _, n_in = eval_pair(oracle, rc * (1.0 - 1e-9), eps, sigma, rc, axis, across_face)
+    assert n_in == 1
+    assert abs(E_in) < 1e-7 * eps
+    # At and beyond rc the pair is dropped entirely (strict r < rc).
+    for r in (rc * (1 + 1e-9), 1.05 * rc):
+        F0, E0, W0, n0 = eval_pair(oracle, r, eps, sigma, rc, axis, across_face)
+        assert n0 == 0 and E0 == 0.0 and W0 == 0.0 and np.all(F0 == 0.0)
+
+
+def test_shift_value_is_minus_energy_at_sigma(oracle):
+    # E(sigma) = V(sigma) - V(rc) = -V(rc); V(rc) < 0 for rc > 2^(1/6) sigma,
+    # and |V(rc)| ~ 4 (sigma/rc)^6 for large rc.
+    for rc in (2.5, 3.0, 5.0):
+        _, E_sig, _, _ = eval_pair(oracle, 1.0, 1.0, 1.0, rc)
+        assert E_sig > 0.0
+        assert E_sig == pytest.approx(4.0 * rc ** -6, rel=2.0 * rc ** -6 + 1e-12)
+
+
+def local_energy(oracle, pos, box, rc, i):
+    """Sum of the shifted pair energy over every j interacting with atom i."""
+    f, e, w, nrs, _ = oracle.sample(pos, box, 1.0, 1.0, rc, rc, np.array([i]))
+    return 2.0 * e[0], f[0], nrs[0]
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_force_is_minus_gradient(oracle, seed):
+    s = synth.small_fcc(5, 1.0, 0.15, seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 100))
+    h = 1e-6
+    rp, col = oracle.cell_pairs(s.pos, s.box, s.rc + s.skin)
+    F, _, _, _ = oracle.forces(s.pos, s.box, 1.0, 1.0, s.rc, rp, col)
+    for i in rng.choice(s.n, size=12, replace=False):
+        _, fi, n0 = local_energy(oracle, s.pos, s.box, s.rc, i)
+        np.testing.assert_allclose(F[i], fi, rtol=0, atol=1e-12 * max(1.0, np.abs(fi).max()))
+        for d in range(3):
+            p = s.pos.copy()
+            p[i, d] += h
+            ep, _, np_ = local_energy(oracle, p, s.box, s.rc, i)
+            p[i, d] -= 2 * h
+            em, _, nm = local_energy(oracle, p, s.box, s.rc, i)
+            if not (np_ == nm == n0):
+                continue       # a pair crossed rc inside the stencil: skip
+            fd = -(ep - em) / (2 * h)
+            assert fd == pytest.approx(F[i, d], abs=2e-6 * max(1.0, abs(F[i, d])))
+
+
+def test_virial_is_minus_scaling_derivative(oracle):
+    s = synth.small_fcc(6, 0.9, 0.12, 3)
+    rs = s.rc + s.skin
+    rp, col = oracle.cell_pairs(s.pos, s.box, rs)
+    _, E0, W, n0 = oracle.forces(s.pos, s.box, 1.0, 1.0, s.rc, rp, col)
+    h = 1e-7
+    _, Ep, _, np_ = oracle.forces(s.pos * (1 + h), s.box * (1 + h), 1.0, 1.0, s.rc, rp, col)
+    _, Em, _, nm = oracle.forces(s.pos * (1 - h), s.box * (1 - h), 1.0, 1.0, s.rc, rp, col)
+    assert np_ == nm == n0
+    fd = -(Ep - Em) / (2 * h)
+    assert fd == pytest.approx(W, rel=1e-6)
+
+
+@pytest.mark.parametrize("maker", [lambda: synth.lj4k(), lambda: synth.small_fcc(7, 0.8, 0.2, 9),
+                                   lambda: synth.small_fcc(6, 1.1, 0.1, 4, rc=2.5)])
+def test_newton_third_law_zero_net_force(oracle, maker):
+    s = maker()
+    rp, col = oracle.cell_pairs(s.pos, s.box, s.rc + s.skin)
+    F, _, _, _ = oracle.forces(s.pos, s.box, 1.0, 1.0, s.rc, rp, col)
+    fmax = np.abs(F).max()
+    assert fmax > 1.0
+    assert np.abs(F.sum(axis=0)).max() <= 1e-12 * fmax * math.sqrt(s.n)
+
+
+def fcc_shell_counts(nshell):
+    """Number of FCC lattice points at squared distance k a^2/2, k = 1..nshell,
+    by enumerating integer lattice vectors (textbook: 12, 6, 24, 12, 24, 8, 48)."""
+    counts = [0] * (nshell + 1)
+    m = int(math.ceil(math.sqrt(nshell / 2.0))) + 1
+    basis = [(0, 0, 0), (1, 1, 0), (1, 0, 1), (0, 1, 1)]  # in units of a/2
+    for bx, by, bz in basis:
+        for i in range(-m, m + 1):
+            for j in range(-m, m + 1):
+                for k in range(-m, m + 1):
+                    x, y, z = 2 * i + bx, 2 * j + by, 2 * k + bz  # a/2 units
+                    q = x * x + y * y + z * z                  # in (a/2)^2 = a^2/4
+                    if q == 0 or q % 2:
+                        continue
+                    if q // 2 <= nshell:
+                        counts[q // 2] += 1
+    return counts[1:]
+
+
+def test_fcc_shell_counts_textbook():
+    assert fcc_shell_counts(7) == [12, 6, 24, 12, 24, 8, 48]
+
+
+@pytest.mark.parametrize("rho", [1.0, 0.85])
+def test_perfect_fcc_neighbor_shells(oracle, rho):
+    s = synth.small_fcc(6, rho, 0.0, 0)
+    a = s.box[0] / 6
+    shells = fcc_shell_counts(7)
+    cum = np.cumsum(shells)
+    idx = np.array([0, 17, 333, s.n - 1])
+    for k in range(7):
+        # radius between shell k+1 and k+2 (squared radii (k+1) a^2/2 and (k+2) a^2/2)
+        R = a * math.sqrt((k + 1.5) / 2.0)
+        _, _, _, nrs, _ = oracle.sample(s.pos, s.box, 1.0, 1.0, R, R, idx)
+        assert np.all(nrs == cum[k]), (k, nrs, cum[k])
+
+
+def lattice_energy_per_atom(rho, rc):
+    """E/N of a perfect FCC crystal, 1/2 sum over lattice vectors R != 0 with
+    |R| < rc of the truncated, shifted 12-6 potential (sigma = eps = 1)."""
+    a = (4.0 / rho) ** (1.0 / 3.0)
+    vc = 4.0 * (rc ** -12 - rc ** -6)
+    basis = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]]) * a
+    m = int(math.ceil(rc / a)) + 1
+    g = np.arange(-m, m + 1) * a
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    cells = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    R = (cells[:, None, :] + basis[None, :, :]).reshape(-1, 3)
+    r = np.sqrt(np.sum(R * R, axis=1))
+    r = r[(r > 0) & (r < rc)]
+    v = 4.0 * (r ** -12 - r ** -6) - vc
+    return 0.5 * math.fsum(v.tolist())
+
+
+@pytest.mark.parametrize("rho,rc,n", [(1.0, 3.0, 6), (0.85, 2.5, 5), (0.9, 2.8, 6)])
+def test_perfect_fcc_lattice_sum(oracle, rho, rc, n):
+    s = synth.small_fcc(n, rho, 0.0, 0, rc=rc)
+    rp, col = oracle.cell_pairs(s.pos, s.box, rc + 0.3)
+    F, E, W, nin = oracle.forces(s.pos, s.box, 1.0, 1.0, rc, rp, col)
+    assert np.abs(F).max() < 1e-11          # every atom is a centre of symmetry
+    assert E / s.n == pytest.approx(lattice_energy_per_atom(rho, rc), rel=1e-12)
+
+
+def test_lattice_energy_values():
+    # Independent of the oracle: the two benchmark states give the cohesive
+    # energies -7.7624 (rho 1, rc 3) and -6.3831 (rho 0.85, rc 2.5).
+    assert lattice_energy_per_atom(1.0, 3.0) == pytest.approx(-7.762386540, abs=1e-8)
+    assert lattice_energy_per_atom(0.85, 2.5) == pytest.approx(-6.383146016, abs=1e-8)
+
+
+CASES = [
+    ("lj4k", lambda: synth.lj4k(), None),
+    ("fcc5-rs3.3", lambda: synth.small_fcc(5, 1.0, 0.2, 11), None),
+    ("fcc4-nc2", lambda: synth.small_fcc(4, 0.7, 0.3, 12, rc=2.9), None),       # 2 cells per dim
+    ("vac-nc1", lambda: synth.vacancy_system(300, 0.8, 0.1, np.random.Generator(
+        np.random.PCG64(5)), 2.5, 0.3, None), None),
+    ("vac-wide", lambda: synth.vacancy_system(2000, 1.1, 0.05, np.random.Generator(
+        np.random.PCG64(6)), 2.5, 0.3, None), None),
+    # strongly disordered: jitter of ~0.45 lattice constants breaks every shell
+    ("disordered", lambda: synth.small_fcc(7, 1.0, 0.7, 13), None),
+    ("disordered-nc4", lambda: synth.small_fcc(9, 0.8, 0.8, 14, rc=2.5), None),
+]
+
+
+@pytest.mark.parametrize("name,maker,_", CASES, ids=[c[0] for c in CASES])
+def test_cell_list_equals_definition(oracle, name, maker, _):
+    s = maker()
+    rs = s.rc + s.skin
+    assert s.box[0] >= 2 * rs
+    a = oracle.brute_pairs(s.pos, s.box, rs)
+    b = oracle.cell_pairs(s.pos, s.box, rs)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert a[1].size > 0
+
+
+def test_cell_list_equals_definition_131k(oracle):
+    s = synth.lj131k()
+    rs = s.rc + s.skin
+    a = oracle.brute_pairs(s.pos, s.box, rs)
+    b = oracle.cell_pairs(s.pos, s.box, rs)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_list_rows_match_paper_count(oracle):
+    # The paper quotes roughly 55 to 80 j atoms per i atom for its benchmark
+    # (FCC, rho = 1, rc = 3, Sec. V.D).  The half list at rs = 3.3 over a
+    # jittered lattice gives rows in that range on average.
+    s = synth.lj4k()
+    rp, col = oracle.cell_pairs(s.pos, s.box, s.rc + s.skin)
+    rows = np.diff(rp)
+    assert 55 <= rows.mean() <= 80
+    # every unordered pair once: row sums of a half list are half the full count
+    _, _, _, nrs, _ = oracle.sample(s.pos, s.box, 1, 1, s.rc, s.rc + s.skin, np.arange(s.n))
+    assert 2 * col.size == int(nrs.sum())
+
+
+def test_permutation_equivariance(oracle):
+    s = synth.lj4k()
+    p = synth.permuted(s, 3)
+    rng = np.random.Generator(np.random.PCG64(3))
+    perm = rng.permutation(s.n)        # p.pos = s.pos[perm]
+    rs = s.rc + s.skin
+    A = half_pairs_set(*oracle.cell_pairs(s.pos, s.box, rs))
+    B = half_pairs_set(*oracle.cell_pairs(p.pos, p.box, rs))
+    Bm = np.sort(perm[B], axis=1)
+    Bm = Bm[np.lexsort((Bm[:, 1], Bm[:, 0]))]
+    assert np.array_equal(A, Bm)
+    Fa, Ea, Wa, na = oracle.forces(s.pos, s.box, 1, 1, s.rc, *oracle.cell_pairs(s.pos, s.box, rs))
+    Fb, Eb, Wb, nb = oracle.forces(p.pos, p.box, 1, 1, s.rc, *oracle.cell_pairs(p.pos, p.box, rs))
+    assert na == nb
+    np.testing.assert_allclose(Fb, Fa[perm], rtol=0, atol=1e-12 * np.abs(Fa).max())
+    assert Eb == pytest.approx(Ea, rel=1e-13)
+    assert Wb == pytest.approx(Wa, rel=1e-13)
+
+
+def test_translation_invariance(oracle):
+    s = synth.small_fcc(6, 1.0, 0.1, 21)
+    rs = s.rc + s.skin
+    shift = np.array([0.3712, -1.25, 2.0031])
+    q = synth.wrap(s.pos + shift, s.box[0])
+    Fa, Ea, Wa, na = oracle.forces(s.pos, s.box, 1, 1, s.rc, *oracle.cell_pairs(s.pos, s.box, rs))
+    Fb, Eb, Wb, nb = oracle.forces(q, s.box, 1, 1, s.rc, *oracle.cell_pairs(q, s.box, rs))
+    assert na == nb
+    np.testing.assert_allclose(Fb, Fa, rtol=0, atol=1e-10 * np.abs(Fa).max())
+    assert Eb == pytest.approx(Ea, rel=1e-12)
+    assert Wb == pytest.approx(Wa, rel=1e-12)
+
+
+def test_full_list_equals_half_list(oracle):
+    # A full list (both (i,j) and (j,i)) visits every pair twice: forces double
+    # ... except that Newton's third law is applied per visit, so F doubles and
+    # E, W double exactly as sums of the same terms.
+    s = synth.small_fcc(5, 1.0, 0.1, 8)
+    rs = s.rc + s.skin
+    rp, col = oracle.cell_pairs(s.pos, s.box, rs)
+    ij = half_pairs_set(rp, col)
+    full = np.concatenate([ij, ij[:, ::-1]])
+    full = full[np.lexsort((full[:, 1], full[:, 0]))]
+    rpf = np.zeros(s.n + 1, dtype=np.int64)
+    np.add.at(rpf, full[:, 0] + 1, 1)
+    rpf = np.cumsum(rpf)
+    F1, E1, W1, n1 = oracle.forces(s.pos, s.box, 1, 1, s.rc, rp, col)
+    F2, E2, W2, n2 = oracle.forces(s.pos, s.box, 1, 1, s.rc, rpf, full[:, 1].astype(np.int32))
+    assert n2 == 2 * n1
+    np.testing.assert_allclose(F2, 2 * F1, rtol=0, atol=1e-12 * np.abs(F1).max())
+    assert E2 == pytest.approx(2 * E1, rel=1e-14)
+    assert W2 == pytest.approx(2 * W1, rel=1e-14)
+
+
+def run_nve(oracle, dt, nsteps, every=10):
+    s = synth.small_fcc(5, 0.85, 0.0, 31, rc=2.5, T=1.0)
+    pos, vel, F, log = oracle.nve(s.pos, s.vel, s.box, 1.0, 1.0, s.rc, s.skin, dt, nsteps, every)
+    return s, log
+
+
+def test_nve_energy_conservation(oracle):
+    s, log = run_nve(oracle, 0.005, 400)
+    etot = log[:, 0] + log[:, 1]
+    assert np.all(np.isfinite(etot))
+    # the lattice melts/heats, so potential and kinetic energy exchange a lot
+    assert np.ptp(log[:, 1]) > 50 * np.ptp(etot)
+    assert abs(etot[-1] - etot[0]) < 2e-3 * abs(etot[0])
+    # displacement since the last build: zero at each rebuild step, growing between
+    assert np.all(log[::10, 3] == 0.0)
+    assert np.all(np.diff(log[1:10, 3]) > 0.0)
+
+
+def test_nve_time_reversible(oracle):
+    s = synth.small_fcc(5, 0.85, 0.05, 32, rc=2.5, T=1.0)
+    p1, v1, _, _ = oracle.nve(s.pos, s.vel, s.box, 1, 1, s.rc, s.skin, 0.004, 100, 10)
+    p2, v2, _, _ = oracle.nve(p1, -v1, s.box, 1, 1, s.rc, s.skin, 0.004, 100, 10)
+    d = p2 - s.pos
+    d -= s.box[0] * np.round(d / s.box[0])
+    assert np.abs(d).max() < 1e-8
+    np.testing.assert_allclose(-v2, s.vel, atol=1e-8)
+
+
+def test_nve_fluctuation_shrinks_with_dt(oracle):
+    _, l1 = run_nve(oracle, 0.004, 250, every=5)
+    _, l2 = run_nve(oracle, 0.002, 500, every=10)
+    e1 = l1[:, 0] + l1[:, 1]
+    e2 = l2[:, 0] + l2[:, 1]
+    assert np.std(e2) < 0.6 * np.std(e1)
