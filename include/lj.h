@@ -1,0 +1,218 @@
+/*
+ * lj.h -- C ABI of the MI355X (gfx950) Lennard-Jones Verlet-list library.
+ *
+ * The library computes the truncated 12-6 Lennard-Jones forces, potential
+ * energy and virial of a periodic system over a Verlet neighbor list, and
+ * builds that list with a cell (linked-list) search.  The method is the one
+ * studied by Watanabe & Nakagawa, "SIMD Vectorization for the Lennard-Jones
+ * Potential with AVX2 and AVX-512 instructions":
+ *   - V(r) = 4 eps [(sigma/r)^12 - (sigma/r)^6], truncated at rc and shifted
+ *     by a constant so that V(rc) = 0 (Sec. III.A, Eq. 1);
+ *   - the Verlet list registers every pair closer than the search length
+ *     rs = rc + skin, built in O(N) with cells, so that it can be reused while
+ *     atoms move less than skin/2; pairs beyond rc are masked at force time
+ *     (Sec. III.B);
+ *   - the list is grouped by i atom ("SortedList", built by a counting sort)
+ *     so that the i data stays in registers over its row (Sec. III.C, Alg. 3);
+ *   - positions may be stored as padded array-of-structures (x, y, z, pad:
+ *     one 32-byte record per atom) or structure-of-arrays (Sec. III, Fig. 1;
+ *     Sec. IV.A, Fig. 6).
+ *
+ * Conventions for every call:
+ *   - Every call returns lj_status; nothing throws or aborts across the ABI.
+ *     On an error the outputs are left untouched and lj_last_error() returns
+ *     a text for the calling thread.
+ *   - Device pointers are HIP device memory on the context's device.  The
+ *     caller owns them (typically torch tensors); the library never frees
+ *     them.  Host pointers are ordinary host memory.
+ *   - Positions: `pos` with `layout`
+ *       LJ_AOS4: n x 4 doubles, record i = (x_i, y_i, z_i, pad), 32-byte aligned;
+ *       LJ_SOA : 3 x n doubles, x block then y block then z block.
+ *     Coordinates must be finite and lie in [0, box[d]).
+ *   - Forces are returned in the same layout as the positions (the pad of
+ *     an LJ_AOS4 record is written as 0).
+ *   - box: host array of 3 box lengths of the periodic, orthorhombic box.
+ *     Every box[d] must be >= 2 (rc + skin) so that the nearest image of a
+ *     pair within the search length is unique (LJ_E_BOX otherwise).
+ *   - Displacement of a pair: t = q_j - q_i per dimension, brought to the
+ *     nearest image; a pair is listed iff |t|^2 < (rc + skin)^2 and
+ *     interacts iff |t|^2 < rc^2 (strict).  The list build evaluates |t|^2 as
+ *     (tx*tx + ty*ty) + tz*tz with every operation rounded on its own, so the
+ *     set of listed pairs is exactly that of this definition.
+ *   - Work is enqueued on the context's HIP stream and is asynchronous unless
+ *     a call says otherwise.  A context must be used by one host thread at a
+ *     time; two calls that overlap on one context race.
+ */
+#ifndef LJ_H
+#define LJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(LJ_BUILD)
+#define LJ_API __attribute__((visibility("default")))
+#else
+#define LJ_API
+#endif
+
+typedef enum {
+    LJ_OK = 0,
+    LJ_E_INVALID = -1,   /* NULL pointer, n < 1, rc <= 0, skin < 0, eps/sigma <= 0,
+                            non-finite parameter, unknown enum value */
+    LJ_E_BOX = -2,       /* some box[d] < 2 (rc + skin) */
+    LJ_E_POSITION = -3,  /* a coordinate is non-finite or outside [0, box[d]) */
+    LJ_E_CAPACITY = -4,  /* a fixed capacity was exceeded (see the call) */
+    LJ_E_STALE = -5,     /* the list does not match the positions or parameters */
+    LJ_E_NOMEM = -6,     /* device or host allocation failed */
+    LJ_E_HIP = -7,       /* a HIP runtime call failed */
+    LJ_E_NODEVICE = -8   /* no usable gfx950 device */
+} lj_status;
+
+/* list kinds */
+#define LJ_LIST_HALF 0   /* each unordered pair once; forces use Newton's third law
+                            and scatter to j with atomic adds (Alg. 3) */
+#define LJ_LIST_FULL 1   /* each pair in both rows; no atomics, every row owns its sum */
+/* precisions */
+#define LJ_FP64 0        /* every operation in FP64 */
+#define LJ_MIXED 1       /* displacement, r^2 and the cutoff test in FP64; the pair
+                            terms ((sigma/r)^2, ^6, the force factor and pair energy)
+                            in FP32; per-atom force, energy and virial accumulated
+                            in FP64 */
+/* position / force layouts */
+#define LJ_AOS4 0
+#define LJ_SOA 1
+
+typedef struct lj_ctx lj_ctx;
+typedef struct lj_cells lj_cells;
+typedef struct lj_list lj_list;
+
+/* Description of a built list (lj_list_info). */
+typedef struct {
+    int64_t n;            /* atoms (rows) */
+    int32_t kind;         /* LJ_LIST_HALF or LJ_LIST_FULL */
+    int32_t lanes;        /* lanes of a 64-wide wavefront that share one row */
+    int32_t cap;          /* entries reserved per row */
+    int32_t max_row;      /* longest row */
+    int64_t entries;      /* stored (i, j) entries: pairs (half) or 2 x pairs (full) */
+    int64_t slots;        /* entries including the padding of each wavefront slice */
+    double rc, skin;      /* cutoff and skin the list was built for */
+    double box[3];        /* box it was built in */
+    int32_t nc[3];        /* cells per dimension used by the search */
+} lj_list_desc;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`.  `stream` is a hipStream_t (NULL =
+ * the null stream); it is not owned.  Fails with LJ_E_NODEVICE if the device
+ * is missing or is not gfx950. */
+LJ_API lj_status lj_create(int device, void* stream, lj_ctx** out);
+LJ_API lj_status lj_destroy(lj_ctx* ctx);
+/* Point the context at another stream (not owned). */
+LJ_API lj_status lj_set_stream(lj_ctx* ctx, void* stream);
+/* Wait for the context's stream and report device-side errors raised by
+ * asynchronous calls since the last check (LJ_E_POSITION, LJ_E_CAPACITY). */
+LJ_API lj_status lj_sync(lj_ctx* ctx);
+
+/* ------------------------------------------------------------------ cells */
+
+/* Bin the atoms into a grid of cells of side >= min_cell per dimension
+ * (cells per dimension nc[d] = the largest count whose side is >= min_cell)
+ * and sort them by cell with a stable counting sort: atoms of a cell are
+ * contiguous and in ascending index (the linked-list method of Sec. III.B and
+ * the counting sort of Sec. III.C, in array form).  Synchronous: positions
+ * are validated and LJ_E_POSITION is returned for a bad coordinate.  *cells
+ * is owned by the library until lj_cells_free. */
+LJ_API lj_status lj_build_cells(lj_ctx* ctx, const double* pos, int64_t n, int32_t layout,
+                         const double box[3], double min_cell, lj_cells** cells);
+/* Grid shape and atom count of a cell structure. */
+LJ_API lj_status lj_cells_info(const lj_cells* cells, int32_t nc[3], int64_t* n);
+/* Copy the cell structure to the host: cell_start (ncell + 1 entries, atoms
+ * of cell c are order[cell_start[c] .. cell_start[c+1])), order (n entries),
+ * cell ids are (cz * nc[1] + cy) * nc[0] + cx.  Either pointer may be NULL.
+ * Synchronous. */
+LJ_API lj_status lj_cells_export(lj_ctx* ctx, const lj_cells* cells, int32_t* cell_start,
+                          int32_t* order);
+LJ_API lj_status lj_cells_free(lj_cells* cells);
+
+/* --------------------------------------------------------------- the list */
+
+/* Build the Verlet list of pairs closer than rs = rc + skin (Sec. III.B).
+ * kind: LJ_LIST_HALF or LJ_LIST_FULL.  lanes: lanes of a wavefront that share
+ * one row in the force kernel (1, 2, 4, 8, 16, 32 or 64; 0 = the library's
+ * tuned choice); the list is laid out for that width.  cells: a structure
+ * from lj_build_cells on the same positions with cells of side >= rs, or NULL
+ * to build one internally.  Synchronous (one device-to-host read of the
+ * longest row; the per-row capacity grows and the build repeats if it was
+ * too small).  *list is owned by the library until lj_list_free.
+ * Rows follow the cell order of the atoms; in a half list the pair (a, b)
+ * sits in exactly one of the two rows, chosen so that every row holds about
+ * half of its atom's neighbors. */
+LJ_API lj_status lj_build_neighbors(lj_ctx* ctx, const double* pos, int64_t n, int32_t layout,
+                             const double box[3], double rc, double skin, int32_t kind,
+                             int32_t lanes, const lj_cells* cells, lj_list** list);
+/* Rebuild the list in place for new positions of the same atoms (same n,
+ * box, rc, skin, kind and lanes): the cells are binned and sorted again and
+ * the rows refilled, reusing the list's buffers.  Asynchronous and free of
+ * host synchronisation and allocation (safe inside HIP graph capture after the
+ * list's first update).  A coordinate outside the box or a row longer than the
+ * list's capacity is recorded on the device and reported by the next lj_sync
+ * (LJ_E_POSITION, LJ_E_CAPACITY); after LJ_E_CAPACITY the list's contents are
+ * incomplete and it must be built again with lj_build_neighbors. */
+LJ_API lj_status lj_update_neighbors(lj_ctx* ctx, const double* pos, int64_t n, int32_t layout,
+                                     const double box[3], lj_list* list);
+/* Describe the list.  Synchronous: reads the row statistics of the latest
+ * build or update from the device. */
+LJ_API lj_status lj_list_info(const lj_list* list, lj_list_desc* out);
+/* Copy the list's entries to the host as (i, j) atom-index pairs: ij[2k],
+ * ij[2k+1] for k < *npairs.  cap: capacity of ij in pairs; if it is too small
+ * *npairs receives the required count and LJ_E_CAPACITY is returned.
+ * Synchronous. */
+LJ_API lj_status lj_list_pairs(lj_ctx* ctx, const lj_list* list, int64_t cap, int32_t* ij,
+                        int64_t* npairs);
+LJ_API lj_status lj_list_free(lj_list* list);
+
+/* ----------------------------------------------------------------- forces */
+
+/* Forces, potential energy and virial of the truncated, shifted LJ potential
+ * over the list (Alg. 1 inside the sorted-list loop of Alg. 3, returning the
+ * force rather than the impulse).  For every listed pair with r^2 < rc^2:
+ *   fs = 24 eps (sigma/r)^6 [2 (sigma/r)^6 - 1] / r^2,  F_j += fs t,  F_i -= fs t,
+ *   energy += 4 eps (sigma/r)^6 [(sigma/r)^6 - 1] - V(rc),  virial += fs r^2.
+ * force: device, n records in `layout`.  energy, virial: device, 1 double
+ * each.  npairs: device int64 receiving the number of interacting pairs, or
+ * NULL.  precision: LJ_FP64 or LJ_MIXED.  The list must have been built for
+ * the same n, layout, box and rc (LJ_E_STALE otherwise), and is valid while
+ * no atom has moved more than skin/2 since the build (not checked here).
+ * Asynchronous; energy, virial and npairs are reduced on the device in a
+ * fixed order, so a full list gives bitwise-reproducible results. */
+LJ_API lj_status lj_forces(lj_ctx* ctx, const double* pos, int64_t n, int32_t layout,
+                    const double box[3], double eps, double sigma, double rc,
+                    const lj_list* list, int32_t precision, double* force, double* energy,
+                    double* virial, int64_t* npairs);
+
+/* ---------------------------------------------------------------- profiling */
+
+/* Phases timed by the profiler (HIP events recorded on the context's stream
+ * around each launch). */
+#define LJ_PROF_CELLS 0   /* binning, prefix sum, scatter, per-cell sort */
+#define LJ_PROF_NEIGH 1   /* the list-build kernel */
+#define LJ_PROF_FORCE 2   /* the force kernel */
+#define LJ_PROF_OTHER 3   /* zero fills */
+#define LJ_PROF_N 4
+/* Start recording (drops anything recorded before). */
+LJ_API lj_status lj_profile_begin(lj_ctx* ctx);
+/* Stop recording, wait for the stream and return, per phase, the summed
+ * device time in milliseconds and the number of launches (arrays of
+ * LJ_PROF_N entries, host).  At most 65,536 launches are recorded. */
+LJ_API lj_status lj_profile_end(lj_ctx* ctx, double* ms, int64_t* launches);
+
+/* Text of the last error on the calling thread ("" if none). */
+LJ_API const char* lj_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LJ_H */

@@ -1,0 +1,317 @@
+// lj_force.hip -- LJ forces, energy and virial over the wavefront-sliced
+// Verlet list (Alg. 1 inside the sorted-list loop of Alg. 3).
+//
+// One wavefront serves one slice: C = 64 / G rows, G lanes per row.  As in
+// Alg. 3 the i atom's position and force stay in registers for the whole row;
+// each lane walks every G-th entry of its row:
+//   j      = col[slot]                 one coalesced 256-byte load per wavefront
+//   q_j    = pos[j]                    gather (double4: one 32-byte record)
+//   t      = q_j - q_i, nearest image  t -= L * rint(t / L)
+//   r^2    = (tx*tx + ty*ty) + tz*tz   rounded as in the list build, so the
+//                                      cutoff test selects exactly the pairs
+//                                      r^2 < rc^2 of the definition
+//   mask   = entry inside the row  and  r^2 < rc^2   (the masks of Fig. 8 and
+//            of the remainder-loop elimination of Alg. 4: no remainder loop)
+//   fs     = 24 eps (sigma/r)^6 [2 (sigma/r)^6 - 1] / r^2 (0 where masked)
+//   F_i   -= fs t;  half list: F_j += fs t by atomic add (Newton's third law)
+//   E     += 4 eps (sigma/r)^6 [(sigma/r)^6 - 1];  W += fs r^2;  count += mask
+// The row's force is summed over its G lanes with cross-lane shuffles.
+// Energy, virial and the pair count are summed per block in a fixed order,
+// and the last block to finish sums the block partials in a fixed order and
+// writes E = scale * (sum - count * V(rc)), W = scale * sum, count * scale,
+// with scale = 1/2 for a full list (every pair is visited twice).
+#include "lj_internal.h"
+
+namespace {
+
+struct ForceArgs {
+    const double* pos;
+    double* force;
+    int64_t n;
+    int64_t nslices;
+    int S;                   // slots per row in G-wide steps (cap / G)
+    double box[3], inv_box[3];
+    double rc2;
+    double sig2, c4, c24, c48, vc;   // sigma^2, 4 eps, 24 eps, 48 eps, V(rc)
+    float sig2f, c4f, c24f, c48f;
+    const int32_t* row_atom;
+    const int32_t* row_len;
+    const int32_t* slice_iters;
+    const int32_t* col;
+    double* partials;        // 4 doubles per block
+    lj_dev_status* st;
+    double* energy;
+    double* virial;
+    int64_t* npairs;
+    double scale;
+};
+
+__device__ __forceinline__ double r2_rounded(double x, double y, double z) {
+#pragma clang fp contract(off)
+    return (x * x + y * y) + z * z;
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ void load_q(const double* __restrict__ pos, int64_t n, int64_t i,
+                                       double& x, double& y, double& z) {
+    if (LAYOUT == LJ_AOS4) {
+        const double4 q = reinterpret_cast<const double4*>(pos)[i];
+        x = q.x;
+        y = q.y;
+        z = q.z;
+    } else {
+        x = pos[i];
+        y = pos[n + i];
+        z = pos[2 * n + i];
+    }
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ void add_f(double* __restrict__ f, int64_t n, int64_t i, double x,
+                                      double y, double z) {
+    if (LAYOUT == LJ_AOS4) {
+        unsafeAtomicAdd(f + 4 * i + 0, x);
+        unsafeAtomicAdd(f + 4 * i + 1, y);
+        unsafeAtomicAdd(f + 4 * i + 2, z);
+    } else {
+        unsafeAtomicAdd(f + i, x);
+        unsafeAtomicAdd(f + n + i, y);
+        unsafeAtomicAdd(f + 2 * n + i, z);
+    }
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ void store_f(double* __restrict__ f, int64_t n, int64_t i, double x,
+                                        double y, double z) {
+    if (LAYOUT == LJ_AOS4) {
+        reinterpret_cast<double4*>(f)[i] = make_double4(x, y, z, 0.0);
+    } else {
+        f[i] = x;
+        f[n + i] = y;
+        f[2 * n + i] = z;
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, LJ_WAVE);
+    return v;
+}
+
+// Block partials (E, W, count) -> partials[block]; the last block to arrive
+// reduces all partials in index order and writes the outputs.
+__device__ void finish_reduction(const ForceArgs& a, double e, double w, double cnt) {
+    __shared__ double red[LJ_WAVES_PER_BLOCK][3];
+    __shared__ bool last;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    e = wave_sum(e);
+    w = wave_sum(w);
+    cnt = wave_sum(cnt);
+    if (lane == 0) {
+        red[wave][0] = e;
+        red[wave][1] = w;
+        red[wave][2] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double be = 0.0, bw = 0.0, bc = 0.0;
+        for (int k = 0; k < LJ_WAVES_PER_BLOCK; ++k) {
+            be += red[k][0];
+            bw += red[k][1];
+            bc += red[k][2];
+        }
+        double* p = a.partials + 4 * (int64_t)blockIdx.x;
+        p[0] = be;
+        p[1] = bw;
+        p[2] = bc;
+        __threadfence();
+        const unsigned prev = atomicAdd(&a.st->done_blocks, 1u);
+        last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    // fixed-order sum: thread t takes blocks t, t + 256, ..., then a tree
+    double se = 0.0, sw = 0.0, sc = 0.0;
+    for (int64_t b = threadIdx.x; b < gridDim.x; b += LJ_BLOCK) {
+        const double* p = a.partials + 4 * b;
+        se += __builtin_nontemporal_load(p + 0);
+        sw += __builtin_nontemporal_load(p + 1);
+        sc += __builtin_nontemporal_load(p + 2);
+    }
+    se = wave_sum(se);
+    sw = wave_sum(sw);
+    sc = wave_sum(sc);
+    __syncthreads();
+    if (lane == 0) {
+        red[wave][0] = se;
+        red[wave][1] = sw;
+        red[wave][2] = sc;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double te = 0.0, tw = 0.0, tc = 0.0;
+        for (int k = 0; k < LJ_WAVES_PER_BLOCK; ++k) {
+            te += red[k][0];
+            tw += red[k][1];
+            tc += red[k][2];
+        }
+        *a.energy = a.scale * (te - tc * a.vc);
+        *a.virial = a.scale * tw;
+        if (a.npairs) *a.npairs = (int64_t)(a.scale * tc + 0.5);
+        a.st->done_blocks = 0u;
+    }
+}
+
+template <int G, bool HALF, int LAYOUT, int PREC>
+__global__ __launch_bounds__(LJ_BLOCK) void k_force(ForceArgs a) {
+    constexpr int C = LJ_WAVE / G;
+    const int lane = threadIdx.x & (LJ_WAVE - 1);
+    const int64_t slice =
+        lj_xcd_block(blockIdx.x, gridDim.x) * LJ_WAVES_PER_BLOCK + (threadIdx.x >> 6);
+    const bool slice_ok = slice < a.nslices;
+    const int c = lane / G, g = lane % G;
+    const int64_t r = slice * C + c;
+    const int64_t i = slice_ok ? a.row_atom[r] : 0;
+    const int len = slice_ok ? a.row_len[r] : 0;
+    const int iters = slice_ok ? a.slice_iters[slice] : 0;
+    double qx, qy, qz;
+    load_q<LAYOUT>(a.pos, a.n, i, qx, qy, qz);
+
+    const int32_t* __restrict__ cp = a.col + (slice_ok ? slice : 0) * (int64_t)a.S * LJ_WAVE + lane;
+    double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0, cnt = 0.0;
+    for (int it = 0; it < iters; ++it) {
+        const int64_t j = cp[(int64_t)it * LJ_WAVE];
+        double px, py, pz;
+        load_q<LAYOUT>(a.pos, a.n, j, px, py, pz);
+        double tx = px - qx, ty = py - qy, tz = pz - qz;
+        tx = fma(-rint(tx * a.inv_box[0]), a.box[0], tx);
+        ty = fma(-rint(ty * a.inv_box[1]), a.box[1], ty);
+        tz = fma(-rint(tz * a.inv_box[2]), a.box[2], tz);
+        const double r2 = r2_rounded(tx, ty, tz);
+        const bool m = (it * G + g < len) && (r2 < a.rc2);
+        double fs;
+        if (PREC == LJ_FP64) {
+            const double ir2 = m ? 1.0 / r2 : 0.0;
+            const double sr2 = a.sig2 * ir2;
+            const double sr6 = sr2 * sr2 * sr2;
+            fs = ir2 * sr6 * (a.c48 * sr6 - a.c24);
+            e += sr6 * (a.c4 * sr6 - a.c4);
+        } else {
+            const float ir2 = m ? __builtin_amdgcn_rcpf((float)r2) : 0.0f;
+            const float sr2 = a.sig2f * ir2;
+            const float sr6 = sr2 * sr2 * sr2;
+            fs = (double)(ir2 * sr6 * (a.c48f * sr6 - a.c24f));
+            e += (double)(sr6 * (a.c4f * sr6 - a.c4f));
+        }
+        w += fs * r2;
+        cnt += m ? 1.0 : 0.0;
+        fx -= fs * tx;
+        fy -= fs * ty;
+        fz -= fs * tz;
+        if (HALF && m) add_f<LAYOUT>(a.force, a.n, j, fs * tx, fs * ty, fs * tz);
+    }
+    // sum the row over its G lanes
+#pragma unroll
+    for (int d = G / 2; d >= 1; d >>= 1) {
+        fx += __shfl_xor(fx, d, LJ_WAVE);
+        fy += __shfl_xor(fy, d, LJ_WAVE);
+        fz += __shfl_xor(fz, d, LJ_WAVE);
+    }
+    if (slice_ok && g == 0 && r < a.n) {
+        if (HALF)
+            add_f<LAYOUT>(a.force, a.n, i, fx, fy, fz);
+        else
+            store_f<LAYOUT>(a.force, a.n, i, fx, fy, fz);
+    }
+    finish_reduction(a, e, w, cnt);
+}
+
+template <int G>
+lj_status launch_g(lj_ctx* ctx, const ForceArgs& a, bool half, int layout, int prec,
+                   int64_t blocks) {
+    dim3 grid((unsigned)blocks), block(LJ_BLOCK);
+    hipStream_t s = ctx->stream;
+#define LJ_K(H, L, P) hipLaunchKernelGGL((k_force<G, H, L, P>), grid, block, 0, s, a)
+    if (half) {
+        if (layout == LJ_AOS4) {
+            if (prec == LJ_FP64) LJ_K(true, LJ_AOS4, LJ_FP64); else LJ_K(true, LJ_AOS4, LJ_MIXED);
+        } else {
+            if (prec == LJ_FP64) LJ_K(true, LJ_SOA, LJ_FP64); else LJ_K(true, LJ_SOA, LJ_MIXED);
+        }
+    } else {
+        if (layout == LJ_AOS4) {
+            if (prec == LJ_FP64) LJ_K(false, LJ_AOS4, LJ_FP64); else LJ_K(false, LJ_AOS4, LJ_MIXED);
+        } else {
+            if (prec == LJ_FP64) LJ_K(false, LJ_SOA, LJ_FP64); else LJ_K(false, LJ_SOA, LJ_MIXED);
+        }
+    }
+#undef LJ_K
+    LJ_HIP(hipGetLastError());
+    return LJ_OK;
+}
+
+}  // namespace
+
+int64_t lj_force_blocks(int64_t nslices) {
+    return (nslices + LJ_WAVES_PER_BLOCK - 1) / LJ_WAVES_PER_BLOCK;
+}
+
+lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, const lj_list* l,
+                           const lj_force_params& p, double* force, double* energy,
+                           double* virial, int64_t* npairs) {
+    const int64_t blocks = lj_force_blocks(l->nslices);
+    if (blocks > ctx->partials_cap) return lj_fail(LJ_E_INVALID, "context partials too small");
+    const bool half = l->kind == LJ_LIST_HALF;
+    if (half) {
+        lj_prof_scope prof(ctx, LJ_PROF_OTHER);
+        const int64_t bytes = (int64_t)sizeof(double) * (p.layout == LJ_AOS4 ? 4 : 3) * l->n;
+        lj_status st = lj_launch_zero(ctx->stream, force, bytes);
+        if (st) return st;
+    }
+    ForceArgs a;
+    a.pos = pos;
+    a.force = force;
+    a.n = l->n;
+    a.nslices = l->nslices;
+    a.S = l->cap / l->lanes;
+    for (int d = 0; d < 3; ++d) {
+        a.box[d] = p.box[d];
+        a.inv_box[d] = 1.0 / p.box[d];
+    }
+    a.rc2 = p.rc * p.rc;
+    a.sig2 = p.sigma * p.sigma;
+    a.c4 = 4.0 * p.eps;
+    a.c24 = 24.0 * p.eps;
+    a.c48 = 48.0 * p.eps;
+    {
+        const double s2 = a.sig2 / a.rc2;
+        const double s6 = s2 * s2 * s2;
+        a.vc = 4.0 * p.eps * s6 * (s6 - 1.0);
+    }
+    a.sig2f = (float)a.sig2;
+    a.c4f = (float)a.c4;
+    a.c24f = (float)a.c24;
+    a.c48f = (float)a.c48;
+    a.row_atom = l->row_atom;
+    a.row_len = l->row_len;
+    a.slice_iters = l->slice_iters;
+    a.col = l->col;
+    a.partials = ctx->partials;
+    a.st = ctx->st;
+    a.energy = energy;
+    a.virial = virial;
+    a.npairs = npairs;
+    a.scale = half ? 1.0 : 0.5;
+    lj_prof_scope prof(ctx, LJ_PROF_FORCE);
+    switch (l->lanes) {
+        case 1: return launch_g<1>(ctx, a, half, p.layout, p.precision, blocks);
+        case 2: return launch_g<2>(ctx, a, half, p.layout, p.precision, blocks);
+        case 4: return launch_g<4>(ctx, a, half, p.layout, p.precision, blocks);
+        case 8: return launch_g<8>(ctx, a, half, p.layout, p.precision, blocks);
+        case 16: return launch_g<16>(ctx, a, half, p.layout, p.precision, blocks);
+        case 32: return launch_g<32>(ctx, a, half, p.layout, p.precision, blocks);
+        case 64: return launch_g<64>(ctx, a, half, p.layout, p.precision, blocks);
+        default: return lj_fail(LJ_E_INVALID, "lanes must be 1, 2, 4, 8, 16, 32 or 64");
+    }
+}

@@ -1,0 +1,283 @@
+"""Python binding of the gfx950 LJ library (include/lj.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+Device arrays are torch tensors on a ROCm device; the library reads and
+writes them in place through their data pointers, on torch's current stream
+(or a stream given to `Context`).  The functions carry the C names.
+
+The binding loads paper_1806_05713_amd/liblj.so and raises ImportError-like
+errors if it is missing: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "liblj.so")
+
+LJ_OK = 0
+LJ_E_INVALID, LJ_E_BOX, LJ_E_POSITION, LJ_E_CAPACITY = -1, -2, -3, -4
+LJ_E_STALE, LJ_E_NOMEM, LJ_E_HIP, LJ_E_NODEVICE = -5, -6, -7, -8
+STATUS_NAMES = {0: "LJ_OK", -1: "LJ_E_INVALID", -2: "LJ_E_BOX", -3: "LJ_E_POSITION",
+                -4: "LJ_E_CAPACITY", -5: "LJ_E_STALE", -6: "LJ_E_NOMEM", -7: "LJ_E_HIP",
+                -8: "LJ_E_NODEVICE"}
+LJ_LIST_HALF, LJ_LIST_FULL = 0, 1
+LJ_FP64, LJ_MIXED = 0, 1
+LJ_AOS4, LJ_SOA = 0, 1
+
+# every entry point declared in include/lj.h
+EXPORTS = ["lj_create", "lj_destroy", "lj_set_stream", "lj_sync", "lj_build_cells",
+           "lj_cells_info", "lj_cells_export", "lj_cells_free", "lj_build_neighbors",
+           "lj_update_neighbors", "lj_list_info", "lj_list_pairs", "lj_list_free", "lj_forces",
+           "lj_profile_begin", "lj_profile_end", "lj_last_error"]
+LJ_PROF_CELLS, LJ_PROF_NEIGH, LJ_PROF_FORCE, LJ_PROF_OTHER, LJ_PROF_N = 0, 1, 2, 3, 4
+PROF_PHASES = ("cells", "neigh", "force", "other")
+
+
+class LJError(RuntimeError):
+    def __init__(self, status: int, what: str, text: str):
+        self.status = status
+        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)}: {text}")
+
+
+class ListDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("kind", ctypes.c_int32), ("lanes", ctypes.c_int32),
+                ("cap", ctypes.c_int32), ("max_row", ctypes.c_int32),
+                ("entries", ctypes.c_int64), ("slots", ctypes.c_int64),
+                ("rc", ctypes.c_double), ("skin", ctypes.c_double),
+                ("box", ctypes.c_double * 3), ("nc", ctypes.c_int32 * 3)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_D3 = ctypes.c_double * 3
+
+
+def load(path: str = LIB_PATH):
+    """Load liblj.so and declare the C signatures (no device is touched)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built: run `python -m paper_1806_05713_amd.build`")
+    L = ctypes.CDLL(path)
+    i32, i64, dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    PP = ctypes.POINTER(_VP)
+    sig = {
+        "lj_create": ([ctypes.c_int, _VP, PP]),
+        "lj_destroy": ([_VP]),
+        "lj_set_stream": ([_VP, _VP]),
+        "lj_sync": ([_VP]),
+        "lj_build_cells": ([_VP, _VP, i64, i32, _D3, dbl, PP]),
+        "lj_cells_info": ([_VP, ctypes.POINTER(i32), ctypes.POINTER(i64)]),
+        "lj_cells_export": ([_VP, _VP, _VP, _VP]),
+        "lj_cells_free": ([_VP]),
+        "lj_build_neighbors": ([_VP, _VP, i64, i32, _D3, dbl, dbl, i32, i32, _VP, PP]),
+        "lj_update_neighbors": ([_VP, _VP, i64, i32, _D3, _VP]),
+        "lj_list_info": ([_VP, ctypes.POINTER(ListDesc)]),
+        "lj_profile_begin": ([_VP]),
+        "lj_profile_end": ([_VP, _VP, _VP]),
+        "lj_list_pairs": ([_VP, _VP, i64, _VP, ctypes.POINTER(i64)]),
+        "lj_list_free": ([_VP]),
+        "lj_forces": ([_VP, _VP, i64, i32, _D3, dbl, dbl, dbl, _VP, i32, _VP, _VP, _VP, _VP]),
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.lj_last_error.argtypes = []
+    L.lj_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(st: int, what: str):
+    if st != LJ_OK:
+        raise LJError(st, what, load().lj_last_error().decode())
+
+
+def _box(box) -> ctypes.Array:
+    b = np.asarray(box, dtype=np.float64).reshape(3)
+    return _D3(*[float(x) for x in b])
+
+
+def _ptr(t) -> int:
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError("expected a tensor on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _pos_layout(pos) -> Tuple[int, int]:
+    """(n, layout) from a tensor's shape: (n, 4) -> AOS4, (3, n) -> SOA."""
+    import torch
+    if pos.dtype != torch.float64:
+        raise TypeError("positions must be float64")
+    if pos.dim() == 2 and pos.shape[1] == 4:
+        return int(pos.shape[0]), LJ_AOS4
+    if pos.dim() == 2 and pos.shape[0] == 3:
+        return int(pos.shape[1]), LJ_SOA
+    raise ValueError("positions must be (n, 4) [AOS4] or (3, n) [SOA]")
+
+
+class Context:
+    """lj_create / lj_destroy; binds torch's current stream unless one is given."""
+
+    def __init__(self, device: int = 0, stream=None):
+        import torch
+        L = load()
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        h = _VP()
+        _check(L.lj_create(device, _VP(stream.cuda_stream), ctypes.byref(h)), "lj_create")
+        self.h = h
+
+    def set_stream(self, stream):
+        self.stream = stream
+        _check(load().lj_set_stream(self.h, _VP(stream.cuda_stream)), "lj_set_stream")
+
+    def sync(self):
+        _check(load().lj_sync(self.h), "lj_sync")
+
+    def profile_begin(self):
+        _check(load().lj_profile_begin(self.h), "lj_profile_begin")
+
+    def profile_end(self):
+        """{phase: (ms, launches)} since profile_begin."""
+        ms = np.zeros(LJ_PROF_N, dtype=np.float64)
+        cnt = np.zeros(LJ_PROF_N, dtype=np.int64)
+        _check(load().lj_profile_end(self.h, ms.ctypes.data, cnt.ctypes.data), "lj_profile_end")
+        return {name: (float(ms[k]), int(cnt[k])) for k, name in enumerate(PROF_PHASES)}
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().lj_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Cells:
+    def __init__(self, ctx: Context, h):
+        self.ctx, self.h = ctx, h
+
+    def info(self):
+        nc = (ctypes.c_int32 * 3)()
+        n = ctypes.c_int64()
+        _check(load().lj_cells_info(self.h, nc, ctypes.byref(n)), "lj_cells_info")
+        return tuple(nc), n.value
+
+    def export(self):
+        nc, n = self.info()
+        ncell = nc[0] * nc[1] * nc[2]
+        cs = np.zeros(ncell + 1, dtype=np.int32)
+        order = np.zeros(n, dtype=np.int32)
+        _check(load().lj_cells_export(self.ctx.h, self.h, cs.ctypes.data, order.ctypes.data),
+               "lj_cells_export")
+        return cs, order
+
+    def free(self):
+        if self.h:
+            load().lj_cells_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class NeighborList:
+    def __init__(self, ctx: Context, h):
+        self.ctx, self.h = ctx, h
+
+    def info(self) -> ListDesc:
+        d = ListDesc()
+        _check(load().lj_list_info(self.h, ctypes.byref(d)), "lj_list_info")
+        return d
+
+    def pairs(self) -> np.ndarray:
+        """(entries, 2) int32 array of the stored (i, j) entries."""
+        d = self.info()
+        ij = np.zeros((max(d.entries, 1), 2), dtype=np.int32)
+        n = ctypes.c_int64()
+        _check(load().lj_list_pairs(self.ctx.h, self.h, d.entries, ij.ctypes.data,
+                                    ctypes.byref(n)), "lj_list_pairs")
+        return ij[: n.value]
+
+    def free(self):
+        if self.h:
+            load().lj_list_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def lj_build_cells(ctx: Context, pos, box, min_cell: float) -> Cells:
+    n, layout = _pos_layout(pos)
+    h = _VP()
+    _check(load().lj_build_cells(ctx.h, _ptr(pos), n, layout, _box(box), float(min_cell),
+                                 ctypes.byref(h)), "lj_build_cells")
+    return Cells(ctx, h)
+
+
+def lj_build_neighbors(ctx: Context, pos, box, rc: float, skin: float,
+                       kind: int = LJ_LIST_HALF, lanes: int = 0,
+                       cells: Optional[Cells] = None) -> NeighborList:
+    n, layout = _pos_layout(pos)
+    h = _VP()
+    _check(load().lj_build_neighbors(ctx.h, _ptr(pos), n, layout, _box(box), float(rc),
+                                     float(skin), int(kind), int(lanes),
+                                     cells.h if cells is not None else None, ctypes.byref(h)),
+           "lj_build_neighbors")
+    return NeighborList(ctx, h)
+
+
+def lj_update_neighbors(ctx: Context, pos, box, nlist: NeighborList) -> NeighborList:
+    """Rebuild nlist in place for new positions (asynchronous)."""
+    n, layout = _pos_layout(pos)
+    _check(load().lj_update_neighbors(ctx.h, _ptr(pos), n, layout, _box(box), nlist.h),
+           "lj_update_neighbors")
+    return nlist
+
+
+def lj_forces(ctx: Context, pos, box, eps: float, sigma: float, rc: float,
+              nlist: NeighborList, precision: int = LJ_FP64, force=None, out=None):
+    """Launch the force kernel (asynchronous).  force: tensor shaped like pos
+    (allocated if None); out: float64 device tensor of 2 receiving energy and
+    virial (allocated if None).  Returns (force, energy, virial, npairs) as
+    device tensors."""
+    import torch
+    n, layout = _pos_layout(pos)
+    if force is None:
+        force = torch.empty_like(pos)
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=pos.device)
+    cnt = torch.empty(1, dtype=torch.int64, device=pos.device)
+    _check(load().lj_forces(ctx.h, _ptr(pos), n, layout, _box(box), float(eps), float(sigma),
+                            float(rc), nlist.h, int(precision), _ptr(force), _ptr(out),
+                            out.data_ptr() + 8, _ptr(cnt)), "lj_forces")
+    return force, out[0:1], out[1:2], cnt
+
+
+def lj_last_error() -> str:
+    return load().lj_last_error().decode()

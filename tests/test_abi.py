@@ -1,0 +1,61 @@
+"""Host-side checks of the C ABI that need no GPU: the built library loads,
+exports every entry point declared in include/lj.h, and rejects bad
+arguments before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lj.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lj_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_binding_exports():
+    from paper_1806_05713_amd import lj
+    assert declared_functions() == sorted(lj.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1806_05713_amd import lj
+    L = lj.load()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def test_argument_errors_without_device():
+    from paper_1806_05713_amd import lj
+    L = lj.load()
+    out = ctypes.c_void_p()
+    assert L.lj_create(0, None, None) == lj.LJ_E_INVALID
+    assert L.lj_sync(None) == lj.LJ_E_INVALID
+    assert L.lj_set_stream(None, None) == lj.LJ_E_INVALID
+    box = (ctypes.c_double * 3)(10.0, 10.0, 10.0)
+    assert L.lj_build_neighbors(None, None, 10, 0, box, 3.0, 0.3, 0, 0, None,
+                                ctypes.byref(out)) == lj.LJ_E_INVALID
+    assert L.lj_forces(None, None, 10, 0, box, 1.0, 1.0, 3.0, None, 0, None, None, None,
+                       None) == lj.LJ_E_INVALID
+    assert L.lj_list_info(None, None) == lj.LJ_E_INVALID
+    assert L.lj_cells_info(None, None, None) == lj.LJ_E_INVALID
+    assert b"NULL" in L.lj_last_error()
+    # freeing NULL handles is a no-op
+    assert L.lj_list_free(None) == lj.LJ_OK
+    assert L.lj_cells_free(None) == lj.LJ_OK
+    assert L.lj_destroy(None) == lj.LJ_OK
+
+
+def test_create_without_gpu_reports_nodevice():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_1806_05713_amd import lj
+    L = lj.load()
+    out = ctypes.c_void_p()
+    st = L.lj_create(0, None, ctypes.byref(out))
+    assert st == lj.LJ_E_NODEVICE
