@@ -113,7 +113,8 @@ LJ_API lj_status lj_destroy(lj_ctx* ctx);
 /* Point the context at another stream (not owned). */
 LJ_API lj_status lj_set_stream(lj_ctx* ctx, void* stream);
 /* Wait for the context's stream and report device-side errors raised by
- * asynchronous calls since the last check (LJ_E_POSITION, LJ_E_CAPACITY). */
+ * asynchronous calls since the last check (LJ_E_POSITION, LJ_E_CAPACITY);
+ * each error is reported once. */
 LJ_API lj_status lj_sync(lj_ctx* ctx);
 
 /* ------------------------------------------------------------------ cells */
@@ -174,6 +175,23 @@ LJ_API lj_status lj_list_pairs(lj_ctx* ctx, const lj_list* list, int64_t cap, in
                         int64_t* npairs);
 LJ_API lj_status lj_list_free(lj_list* list);
 
+/* Read-only device view of a list's layout, for kernels of the caller that
+ * consume the list directly.  Rows are the atoms in cell order, grouped in
+ * slices of C = 64 / lanes rows; entry k of row c of slice s is
+ *   col[(s * (cap / lanes) + k / lanes) * 64 + c * lanes + k % lanes]
+ * for k < row_len[s * C + c]; slots past a row's length up to lanes *
+ * slice_iters[s] hold the row's own atom.  row_atom[r] is the atom of row r.
+ * The pointers stay valid until the list is rebuilt or freed. */
+typedef struct {
+    const int32_t* col;
+    const int32_t* row_atom;     /* nslices * C */
+    const int32_t* row_len;      /* nslices * C */
+    const int32_t* slice_iters;  /* nslices */
+    int64_t nslices;
+    int32_t lanes, cap;
+} lj_list_view;
+LJ_API lj_status lj_list_device_view(const lj_list* list, lj_list_view* out);
+
 /* ----------------------------------------------------------------- forces */
 
 /* Forces, potential energy and virial of the truncated, shifted LJ potential
@@ -192,6 +210,23 @@ LJ_API lj_status lj_forces(lj_ctx* ctx, const double* pos, int64_t n, int32_t la
                     const double box[3], double eps, double sigma, double rc,
                     const lj_list* list, int32_t precision, double* force, double* energy,
                     double* virial, int64_t* npairs);
+
+/* ------------------------------------------------------------------ tuning */
+
+/* Launch-shape knobs of a context, set by the autotuner (or by hand).  They
+ * change only speed, never results: every setting computes the same list
+ * (as a set) and the same forces.  0 selects the library's default. */
+#define LJ_TUNE_BUILD_LANES 0   /* lanes per row in the list-build kernel: 1, 2 or 4
+                                   (at most the list's lanes); default 1 */
+#define LJ_TUNE_FORCE_BATCH 1   /* list entries each lane has in flight in the force
+                                   kernel: 2, 4 or 8; default 4 */
+#define LJ_TUNE_CELL_DIV 2      /* lists built without caller cells use cells of side
+                                   (rc + skin) / k, k = 1, 2, 3 or 4; default 2 */
+#define LJ_TUNE_N 3
+/* Set knob `knob` to `value` (LJ_E_INVALID for an unknown knob or value). */
+LJ_API lj_status lj_tune_set(lj_ctx* ctx, int32_t knob, int32_t value);
+/* Current value of a knob (0 = default). */
+LJ_API lj_status lj_tune_get(const lj_ctx* ctx, int32_t knob, int32_t* value);
 
 /* ---------------------------------------------------------------- profiling */
 

@@ -1,0 +1,117 @@
+"""Autotuner for the launch shapes of the LJ library.
+
+The knobs change speed only -- every setting yields the same list (as a set)
+and the same forces -- so tuning is a search over timings:
+  lanes        lanes of a 64-wide wavefront per row of the list layout (force kernel)
+  build_lanes  lanes per row in the list-build kernel (LJ_TUNE_BUILD_LANES)
+  batch        list entries each lane keeps in flight in the force kernel
+               (LJ_TUNE_FORCE_BATCH)
+  cell_div     list-build cells of side (rc + skin) / cell_div (LJ_TUNE_CELL_DIV)
+
+Each candidate is timed with the library's own HIP-event profiler on the
+context's stream (device time of the list-build and force kernels).  Results
+are cached as JSON keyed by device name, CU count, atom-count bucket,
+density, search length, list kind and precision.
+"""
+from __future__ import annotations
+
+import itertools
+import json
+import math
+import os
+from typing import Dict, Iterable, Optional
+
+from . import lj
+
+CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+SPACE = {
+    "lanes": (4, 8, 16),
+    "build_lanes": (1, 2, 4),
+    "batch": (2, 4, 8),
+    "cell_div": (1, 2, 3),
+}
+
+
+def key(device_name: str, cus: int, n: int, rho: float, rs: float, kind: int,
+        precision: int) -> str:
+    nb = int(round(math.log2(max(n, 1))))
+    return f"{device_name}/{cus}cu/n2^{nb}/rho{rho:.2f}/rs{rs:.2f}/k{kind}/p{precision}"
+
+
+def load_cache(path: str = CACHE) -> Dict[str, dict]:
+    if os.path.exists(path):
+        with open(path) as f:
+            return json.load(f)
+    return {}
+
+
+def save_cache(cache: Dict[str, dict], path: str = CACHE) -> None:
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def apply(ctx: "lj.Context", cfg: dict) -> None:
+    ctx.tune_set(lj.LJ_TUNE_BUILD_LANES, cfg.get("build_lanes", 0))
+    ctx.tune_set(lj.LJ_TUNE_FORCE_BATCH, cfg.get("batch", 0))
+    ctx.tune_set(lj.LJ_TUNE_CELL_DIV, cfg.get("cell_div", 0))
+
+
+def measure(ctx, pos, box, rc, skin, kind, precision, cfg, reps: int = 20) -> dict:
+    """Device time (us) of one list rebuild and one force evaluation with cfg."""
+    import torch
+    apply(ctx, cfg)
+    nl = lj.lj_build_neighbors(ctx, pos, box, rc, skin, kind=kind, lanes=cfg["lanes"])
+    force = torch.empty_like(pos)
+    out = torch.empty(2, dtype=torch.float64, device=pos.device)
+    for _ in range(3):
+        lj.lj_update_neighbors(ctx, pos, box, nl)
+        lj.lj_forces(ctx, pos, box, 1.0, 1.0, rc, nl, precision, force, out)
+    ctx.profile_begin()
+    for _ in range(reps):
+        lj.lj_update_neighbors(ctx, pos, box, nl)
+        lj.lj_forces(ctx, pos, box, 1.0, 1.0, rc, nl, precision, force, out)
+    prof = ctx.profile_end()
+    ctx.sync()
+    nl.free()
+    per = {k: v[0] * 1e3 / max(v[1], 1) for k, v in prof.items()}
+    return {"build_us": per["cells"] + per["neigh"], "force_us": per["force"],
+            "step_us": per["cells"] + per["neigh"] + per["force"] + per["other"]}
+
+
+def tune(ctx, pos, box, rc, skin, kind=lj.LJ_LIST_FULL, precision=lj.LJ_FP64,
+         objective: str = "step_us", space: Optional[dict] = None, reps: int = 20,
+         log=None) -> dict:
+    """Search `space` (default SPACE); returns {"best": cfg, "results": [...]}."""
+    space = dict(SPACE if space is None else space)
+    results = []
+    names = list(space)
+    for vals in itertools.product(*(space[k] for k in names)):
+        cfg = dict(zip(names, vals))
+        if cfg["build_lanes"] > cfg["lanes"]:
+            continue
+        t = measure(ctx, pos, box, rc, skin, kind, precision, cfg, reps)
+        results.append({**cfg, **t})
+        if log:
+            log(json.dumps(results[-1]))
+    best = min(results, key=lambda r: r[objective])
+    return {"best": {k: best[k] for k in names}, "objective": objective, "results": results}
+
+
+def best_config(ctx, pos, box, rc, skin, kind, precision, rho: float,
+                cache_path: str = CACHE, retune: bool = False, log=None) -> dict:
+    """Cached tuned configuration for this device and workload shape."""
+    import torch
+    props = torch.cuda.get_device_properties(pos.device)
+    k = key(getattr(props, "gcnArchName", props.name), props.multi_processor_count,
+            int(pos.numel() // 4 if pos.dim() == 2 and pos.shape[1] == 4 else pos.shape[1]),
+            rho, rc + skin, kind, precision)
+    cache = load_cache(cache_path)
+    if k in cache and not retune:
+        return cache[k]
+    res = tune(ctx, pos, box, rc, skin, kind, precision, log=log)
+    cache[k] = res["best"]
+    save_cache(cache, cache_path)
+    return res["best"]

@@ -155,6 +155,7 @@ void list_release(lj_list* l) {
     dfree(l->row_atom);
     dfree(l->row_len);
     dfree(l->slice_iters);
+    dfree(l->slice_stats);
     dfree(l->col);
     dfree(l->stats);
     cells_release(l->cells);
@@ -166,6 +167,7 @@ lj_status alloc_cells(int64_t n, const double* box, double min_cell, lj_cells** 
     if (!c) return lj_fail(LJ_E_NOMEM, "host allocation");
     c->n = n;
     c->ncell = 1;
+    c->counts_dirty = true;   // fresh allocation: cleared by the first build
     for (int d = 0; d < 3; ++d) {
         c->box[d] = box[d];
         c->nc[d] = cells_for(box[d], min_cell);
@@ -207,6 +209,16 @@ lj_status read_stats(const lj_list* l, hipStream_t s, lj_list_stats* h) {
 
 int default_lanes(int kind) { return kind == LJ_LIST_FULL ? 8 : 8; }
 
+// Side of the cells the library bins into for its own list builds: the search
+// length over k (default k = 2: each row then visits about 2.7x fewer
+// candidates than with a 27-cell stencil of side rs), with a small relative
+// margin so that rounding cannot push the reach of rs + delta to one more cell.
+double internal_min_cell(const lj_ctx* ctx, double rs) {
+    int k = ctx->tune[LJ_TUNE_CELL_DIV];
+    if (k < 1 || k > 4) k = 2;
+    return rs / k * (1.0 + 1e-11);
+}
+
 }  // namespace
 
 // ----------------------------------------------------------------- context
@@ -228,6 +240,7 @@ extern "C" lj_status lj_create(int device, void* stream, lj_ctx** out) {
     ctx->device = device;
     ctx->stream = (hipStream_t)stream;
     ctx->prof_on = false;
+    for (int k = 0; k < LJ_TUNE_N; ++k) ctx->tune[k] = 0;
     lj_status st = dmalloc(&ctx->st, 1);
     if (st) {
         delete ctx;
@@ -274,6 +287,10 @@ extern "C" lj_status lj_sync(lj_ctx* ctx) {
     lj_dev_status h;
     lj_status st = read_status(ctx, &h);
     if (st) return st;
+    if (h.flags) {   // report once: clear the flags
+        if ((st = reset_status(ctx))) return st;
+        LJ_HIP(hipStreamSynchronize(ctx->stream));
+    }
     if (h.flags & LJ_DEV_BAD_POSITION)
         return lj_fail(LJ_E_POSITION, "a coordinate is non-finite or outside [0, box)");
     if (h.flags & (LJ_DEV_ROW_OVERFLOW | LJ_DEV_CELL_OVERFLOW))
@@ -353,8 +370,8 @@ extern "C" lj_status lj_build_neighbors(lj_ctx* ctx, const double* pos, int64_t 
         if (cells->n != n) return lj_fail(LJ_E_STALE, "cells were built for another atom count");
         for (int d = 0; d < 3; ++d) {
             if (cells->box[d] != box[d]) return lj_fail(LJ_E_STALE, "cells were built for another box");
-            if (cells->nc[d] >= 3 && cells->cs[d] < rs * (1.0 + 1e-12))
-                return lj_fail(LJ_E_INVALID, "cells are smaller than rc + skin");
+            if (cells->nc[d] > 1 && cells->cs[d] * 16.0 < rs)
+                return lj_fail(LJ_E_INVALID, "cells are smaller than (rc + skin) / 16");
         }
     }
     lj_list* l = new (std::nothrow) lj_list();
@@ -367,7 +384,7 @@ extern "C" lj_status lj_build_neighbors(lj_ctx* ctx, const double* pos, int64_t 
     for (int d = 0; d < 3; ++d) l->box[d] = box[d];
     const lj_cells* c = cells;
     if (!c) {
-        if ((st = alloc_cells(n, box, rs, &l->cells)) ||
+        if ((st = alloc_cells(n, box, internal_min_cell(ctx, rs), &l->cells)) ||
             (st = fill_cells_sync(ctx, pos, layout, l->cells))) {
             list_release(l);
             return st;
@@ -376,7 +393,9 @@ extern "C" lj_status lj_build_neighbors(lj_ctx* ctx, const double* pos, int64_t 
     }
     for (int d = 0; d < 3; ++d) l->nc[d] = c->nc[d];
     const int C = LJ_WAVE / lanes;
-    l->nslices = (n + C - 1) / C;
+    // whole wavefronts of the build (up to 16 slices each, when it uses fewer
+    // lanes per row than the layout); trailing slices stay empty
+    l->nslices = ((n + C - 1) / C + 15) / 16 * 16;
     // First guess of the row capacity: 1.25 x the neighbors within rs of an
     // atom at the mean density, plus a margin; grown on overflow.
     const double vol = box[0] * box[1] * box[2];
@@ -386,7 +405,8 @@ extern "C" lj_status lj_build_neighbors(lj_ctx* ctx, const double* pos, int64_t 
     if (cap > n) cap = n;
     const int64_t slice_rows = l->nslices * C;
     if ((st = dmalloc(&l->row_atom, slice_rows)) || (st = dmalloc(&l->row_len, slice_rows)) ||
-        (st = dmalloc(&l->slice_iters, l->nslices)) || (st = dmalloc(&l->stats, 1))) {
+        (st = dmalloc(&l->slice_iters, l->nslices)) ||
+        (st = dmalloc(&l->slice_stats, 2 * l->nslices)) || (st = dmalloc(&l->stats, 1))) {
         list_release(l);
         return st;
     }
@@ -445,7 +465,7 @@ extern "C" lj_status lj_update_neighbors(lj_ctx* ctx, const double* pos, int64_t
         if (l->box[d] != box[d]) return lj_fail(LJ_E_STALE, "list was built for another box");
     DeviceGuard guard(ctx->device);
     if (!l->cells) {   // first update of a list built on caller-provided cells
-        if ((st = alloc_cells(n, box, l->rc + l->skin, &l->cells))) return st;
+        if ((st = alloc_cells(n, box, internal_min_cell(ctx, l->rc + l->skin), &l->cells))) return st;
     }
     if ((st = lj_launch_cells(ctx, pos, layout, l->cells))) return st;
     return lj_launch_neighbors(ctx, l->cells, l, l->rc + l->skin);
@@ -524,8 +544,43 @@ extern "C" lj_status lj_list_pairs(lj_ctx* ctx, const lj_list* l, int64_t cap, i
     return st;
 }
 
+extern "C" lj_status lj_list_device_view(const lj_list* l, lj_list_view* out) {
+    if (!l || !out) return lj_fail(LJ_E_INVALID, "list or out is NULL");
+    out->col = l->col;
+    out->row_atom = l->row_atom;
+    out->row_len = l->row_len;
+    out->slice_iters = l->slice_iters;
+    out->nslices = l->nslices;
+    out->lanes = l->lanes;
+    out->cap = l->cap;
+    return LJ_OK;
+}
+
 extern "C" lj_status lj_list_free(lj_list* l) {
     list_release(l);
+    return LJ_OK;
+}
+
+// ------------------------------------------------------------------ tuning
+
+extern "C" lj_status lj_tune_set(lj_ctx* ctx, int32_t knob, int32_t value) {
+    if (!ctx) return lj_fail(LJ_E_INVALID, "context is NULL");
+    bool ok = false;
+    switch (knob) {
+        case LJ_TUNE_BUILD_LANES: ok = value == 0 || value == 1 || value == 2 || value == 4; break;
+        case LJ_TUNE_FORCE_BATCH: ok = value == 0 || value == 2 || value == 4 || value == 8; break;
+        case LJ_TUNE_CELL_DIV: ok = value >= 0 && value <= 4; break;
+        default: return lj_fail(LJ_E_INVALID, "unknown tuning knob");
+    }
+    if (!ok) return lj_fail(LJ_E_INVALID, "value not allowed for this knob");
+    ctx->tune[knob] = value;
+    return LJ_OK;
+}
+
+extern "C" lj_status lj_tune_get(const lj_ctx* ctx, int32_t knob, int32_t* value) {
+    if (!ctx || !value) return lj_fail(LJ_E_INVALID, "context or value is NULL");
+    if (knob < 0 || knob >= LJ_TUNE_N) return lj_fail(LJ_E_INVALID, "unknown tuning knob");
+    *value = ctx->tune[knob];
     return LJ_OK;
 }
 

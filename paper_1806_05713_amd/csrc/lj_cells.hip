@@ -177,6 +177,49 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_scan_sums(int32_t* __restrict__ su
     if (threadIdx.x == 0) *out_total = total;
 }
 
+// Small arrays: one block stages the whole array in LDS with coalesced loads,
+// each thread scans a contiguous chunk there, and the result is written back
+// coalesced.
+constexpr int SCAN1_THREADS = 1024;
+constexpr int64_t SCAN1_MAX = 32768;   // 128 KB of LDS
+__global__ __launch_bounds__(SCAN1_THREADS) void k_scan_single(const int32_t* __restrict__ in,
+                                                               int32_t* __restrict__ out,
+                                                               int64_t m) {
+    __shared__ int buf[SCAN1_MAX];
+    __shared__ int lds[SCAN1_THREADS / 64];
+    for (int64_t k = threadIdx.x; k < m; k += SCAN1_THREADS) buf[k] = in[k];
+    __syncthreads();
+    const int per = (int)((m + SCAN1_THREADS - 1) / SCAN1_THREADS);
+    const int b0 = threadIdx.x * per;
+    int s = 0;
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < m) s += buf[b0 + k];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    int x = s;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) lds[wave] = x;
+    __syncthreads();
+    int off = 0, tot = 0;
+    for (int w = 0; w < SCAN1_THREADS / 64; ++w) {
+        if (w < wave) off += lds[w];
+        tot += lds[w];
+    }
+    int run = off + x - s;
+    for (int k = 0; k < per; ++k)
+        if (b0 + k < m) {
+            const int v = buf[b0 + k];
+            buf[b0 + k] = run;
+            run += v;
+        }
+    __syncthreads();
+    for (int64_t k = threadIdx.x; k < m; k += SCAN1_THREADS) out[k] = buf[k];
+    if (threadIdx.x == 0) out[m] = tot;
+}
+
 __global__ __launch_bounds__(LJ_BLOCK) void k_scan_add(int32_t* __restrict__ out, int64_t m,
                                                        const int32_t* __restrict__ sums) {
     const int add = sums[blockIdx.x];
@@ -208,6 +251,11 @@ lj_status lj_launch_scan(hipStream_t s, const int32_t* in, int32_t* out, int64_t
     const int64_t nt = (m + SCAN_TILE - 1) / SCAN_TILE;
     if (nt > SCAN_TILE) return lj_fail(LJ_E_CAPACITY, "scan: more than 16.7M elements");
     if (m == 0) return lj_launch_zero(s, out, sizeof(int32_t));
+    if (m <= SCAN1_MAX) {
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SCAN1_THREADS), 0, s, in, out, m);
+        LJ_HIP(hipGetLastError());
+        return LJ_OK;
+    }
     hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)nt), dim3(LJ_BLOCK), 0, s, in, out, m, work);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(LJ_BLOCK), 0, s, work, nt, out + m);
     hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nt), dim3(LJ_BLOCK), 0, s, out, m,
@@ -219,8 +267,13 @@ lj_status lj_launch_scan(hipStream_t s, const int32_t* in, int32_t* out, int64_t
 lj_status lj_launch_cells(lj_ctx* ctx, const double* pos, int layout, lj_cells* c) {
     hipStream_t s = ctx->stream;
     lj_prof_scope prof(ctx, LJ_PROF_CELLS);
-    lj_status st = lj_launch_zero(s, c->count, c->ncell * (int64_t)sizeof(int32_t));
-    if (st) return st;
+    lj_status st;
+    // The per-cell counts are zero between builds: the scatter counts each
+    // cell back down to zero.  Clear them only after an interrupted build.
+    if (c->counts_dirty) {
+        if ((st = lj_launch_zero(s, c->count, c->ncell * (int64_t)sizeof(int32_t)))) return st;
+    }
+    c->counts_dirty = true;
     BinArgs a;
     a.pos = pos;
     a.n = c->n;
@@ -240,6 +293,8 @@ lj_status lj_launch_cells(lj_ctx* ctx, const double* pos, int layout, lj_cells* 
     hipLaunchKernelGGL(k_scatter, dim3(grid_for(c->n, LJ_BLOCK)), dim3(LJ_BLOCK), 0, s, c->n,
                        (const int32_t*)c->cid, (const int32_t*)c->cell_start, c->count,
                        c->order_tmp);
+    LJ_HIP(hipGetLastError());
+    c->counts_dirty = false;
     hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(c->ncell, LJ_WAVES_PER_BLOCK)), dim3(LJ_BLOCK),
                        0, s, c->ncell, c->n, (const int32_t*)c->cell_start,
                        (const int32_t*)c->order_tmp, pos, layout, c->order, c->spos);

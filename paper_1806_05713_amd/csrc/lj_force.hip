@@ -14,12 +14,13 @@
 //            of the remainder-loop elimination of Alg. 4: no remainder loop)
 //   fs     = 24 eps (sigma/r)^6 [2 (sigma/r)^6 - 1] / r^2 (0 where masked)
 //   F_i   -= fs t;  half list: F_j += fs t by atomic add (Newton's third law)
-//   E     += 4 eps (sigma/r)^6 [(sigma/r)^6 - 1];  W += fs r^2;  count += mask
+//   A     += (sigma/r)^12, B += (sigma/r)^6, count += mask, so that
+//            E = 4 eps (A - B) - count V(rc) and W = sum fs r^2 = 24 eps (2A - B)
 // The row's force is summed over its G lanes with cross-lane shuffles.
 // Energy, virial and the pair count are summed per block in a fixed order,
-// and the last block to finish sums the block partials in a fixed order and
-// writes E = scale * (sum - count * V(rc)), W = scale * sum, count * scale,
-// with scale = 1/2 for a full list (every pair is visited twice).
+// and a one-block kernel sums the block partials in a fixed order and writes
+// E = scale * (sum - count * V(rc)), W = scale * sum, count * scale, with
+// scale = 1/2 for a full list (every pair is visited twice).
 #include "lj_internal.h"
 
 namespace {
@@ -98,11 +99,12 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Block partials (E, W, count) -> partials[block]; the last block to arrive
-// reduces all partials in index order and writes the outputs.
-__device__ void finish_reduction(const ForceArgs& a, double e, double w, double cnt) {
+// Block partials (E, W, count) -> partials[4 * block], summed in a fixed
+// order.  No atomics: a device-scope atomic must stay coherent across the
+// eight per-XCD L2 caches and is resolved beyond them, so thousands of blocks
+// hitting one counter serialise.
+__device__ void block_partials(const ForceArgs& a, double e, double w, double cnt) {
     __shared__ double red[LJ_WAVES_PER_BLOCK][3];
-    __shared__ bool last;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     e = wave_sum(e);
     w = wave_sum(w);
@@ -124,25 +126,25 @@ __device__ void finish_reduction(const ForceArgs& a, double e, double w, double 
         p[0] = be;
         p[1] = bw;
         p[2] = bc;
-        __threadfence();
-        const unsigned prev = atomicAdd(&a.st->done_blocks, 1u);
-        last = (prev == gridDim.x - 1);
     }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // fixed-order sum: thread t takes blocks t, t + 256, ..., then a tree
+}
+
+// One block: thread t sums partials t, t + 1024, ... then a fixed tree.
+__global__ __launch_bounds__(1024) void k_force_reduce(const double* __restrict__ partials,
+                                                       int64_t nblocks, double scale, double vc,
+                                                       double* energy, double* virial,
+                                                       int64_t* npairs) {
+    __shared__ double red[16][3];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double se = 0.0, sw = 0.0, sc = 0.0;
-    for (int64_t b = threadIdx.x; b < gridDim.x; b += LJ_BLOCK) {
-        const double* p = a.partials + 4 * b;
-        se += __builtin_nontemporal_load(p + 0);
-        sw += __builtin_nontemporal_load(p + 1);
-        sc += __builtin_nontemporal_load(p + 2);
+    for (int64_t b = threadIdx.x; b < nblocks; b += 1024) {
+        se += partials[4 * b + 0];
+        sw += partials[4 * b + 1];
+        sc += partials[4 * b + 2];
     }
     se = wave_sum(se);
     sw = wave_sum(sw);
     sc = wave_sum(sc);
-    __syncthreads();
     if (lane == 0) {
         red[wave][0] = se;
         red[wave][1] = sw;
@@ -151,65 +153,126 @@ __device__ void finish_reduction(const ForceArgs& a, double e, double w, double 
     __syncthreads();
     if (threadIdx.x == 0) {
         double te = 0.0, tw = 0.0, tc = 0.0;
-        for (int k = 0; k < LJ_WAVES_PER_BLOCK; ++k) {
+        for (int k = 0; k < 16; ++k) {
             te += red[k][0];
             tw += red[k][1];
             tc += red[k][2];
         }
-        *a.energy = a.scale * (te - tc * a.vc);
-        *a.virial = a.scale * tw;
-        if (a.npairs) *a.npairs = (int64_t)(a.scale * tc + 0.5);
-        a.st->done_blocks = 0u;
+        *energy = scale * (te - tc * vc);
+        *virial = scale * tw;
+        if (npairs) *npairs = (int64_t)(scale * tc + 0.5);
     }
 }
 
-template <int G, bool HALF, int LAYOUT, int PREC>
+// 1/x as v_rcp_f64 refined by two Newton steps y <- y (2 - x y) (each step
+// squares the relative error, which v_rcp_f64 already bounds far below 2^-20).
+__device__ __forceinline__ double recip(double x) {
+    double y = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, y, 1.0);
+    y = fma(y, e, y);
+    e = fma(-x, y, 1.0);
+    return fma(y, e, y);
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ void gather_q(const double* __restrict__ pos, int64_t n, int j,
+                                         double& x, double& y, double& z) {
+    if (LAYOUT == LJ_AOS4) {
+        // 32-bit byte offset from a uniform base: one dwordx4 + one dwordx2 load
+        const double4* q = reinterpret_cast<const double4*>(
+            reinterpret_cast<const char*>(pos) + (uint32_t)j * 32u);
+        x = q->x;
+        y = q->y;
+        z = q->z;
+    } else {
+        const uint32_t o = (uint32_t)j * 8u;
+        x = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(pos) + o);
+        y = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(pos + n) + o);
+        z = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(pos + 2 * n) + o);
+    }
+}
+
+// Loads are issued U entries at a time, and the indices of the next U
+// entries are requested before the current ones are computed, so each
+// wavefront keeps up to 3U gathers and U index loads in flight (the
+// load/compute overlap that software pipelining gives a CPU core).
+template <int G, bool HALF, int LAYOUT, int PREC, int U>
 __global__ __launch_bounds__(LJ_BLOCK) void k_force(ForceArgs a) {
     constexpr int C = LJ_WAVE / G;
     const int lane = threadIdx.x & (LJ_WAVE - 1);
-    const int64_t slice =
-        lj_xcd_block(blockIdx.x, gridDim.x) * LJ_WAVES_PER_BLOCK + (threadIdx.x >> 6);
+    const int slice = __builtin_amdgcn_readfirstlane(
+        (int)lj_xcd_block(blockIdx.x, gridDim.x) * LJ_WAVES_PER_BLOCK + (threadIdx.x >> 6));
     const bool slice_ok = slice < a.nslices;
+    const int iters = slice_ok ? __builtin_amdgcn_readfirstlane(a.slice_iters[slice]) : 0;
     const int c = lane / G, g = lane % G;
-    const int64_t r = slice * C + c;
-    const int64_t i = slice_ok ? a.row_atom[r] : 0;
-    const int len = slice_ok ? a.row_len[r] : 0;
-    const int iters = slice_ok ? a.slice_iters[slice] : 0;
+    const int r = slice * C + c;
+    int i = 0, lim = 0;
+    if (slice_ok) {
+        i = a.row_atom[r];
+        lim = a.row_len[r] - g;   // entry it*G + g is inside the row iff it*G < lim
+    }
     double qx, qy, qz;
-    load_q<LAYOUT>(a.pos, a.n, i, qx, qy, qz);
+    gather_q<LAYOUT>(a.pos, a.n, i, qx, qy, qz);
 
-    const int32_t* __restrict__ cp = a.col + (slice_ok ? slice : 0) * (int64_t)a.S * LJ_WAVE + lane;
-    double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0, w = 0.0, cnt = 0.0;
-    for (int it = 0; it < iters; ++it) {
-        const int64_t j = cp[(int64_t)it * LJ_WAVE];
-        double px, py, pz;
-        load_q<LAYOUT>(a.pos, a.n, j, px, py, pz);
-        double tx = px - qx, ty = py - qy, tz = pz - qz;
-        tx = fma(-rint(tx * a.inv_box[0]), a.box[0], tx);
-        ty = fma(-rint(ty * a.inv_box[1]), a.box[1], ty);
-        tz = fma(-rint(tz * a.inv_box[2]), a.box[2], tz);
-        const double r2 = r2_rounded(tx, ty, tz);
-        const bool m = (it * G + g < len) && (r2 < a.rc2);
-        double fs;
-        if (PREC == LJ_FP64) {
-            const double ir2 = m ? 1.0 / r2 : 0.0;
-            const double sr2 = a.sig2 * ir2;
-            const double sr6 = sr2 * sr2 * sr2;
-            fs = ir2 * sr6 * (a.c48 * sr6 - a.c24);
-            e += sr6 * (a.c4 * sr6 - a.c4);
-        } else {
-            const float ir2 = m ? __builtin_amdgcn_rcpf((float)r2) : 0.0f;
-            const float sr2 = a.sig2f * ir2;
-            const float sr6 = sr2 * sr2 * sr2;
-            fs = (double)(ir2 * sr6 * (a.c48f * sr6 - a.c24f));
-            e += (double)(sr6 * (a.c4f * sr6 - a.c4f));
+    const char* colbase =
+        reinterpret_cast<const char*>(a.col + (int64_t)(slice_ok ? slice : 0) * a.S * LJ_WAVE);
+    const uint32_t lane_off = (uint32_t)lane * 4u;
+    double fx = 0.0, fy = 0.0, fz = 0.0, sA = 0.0, sB = 0.0;
+    int cnt = 0;
+
+    // slot of step `it`, clamped into the slice so that every index load is
+    // unconditional (no branch for the compiler to wait behind)
+    const int last = iters > 0 ? iters - 1 : 0;
+    auto idx_at = [&](int it) -> int {
+        const int k = it < last ? it : last;
+        return __builtin_nontemporal_load(
+            reinterpret_cast<const int*>(colbase + (uint32_t)(k * LJ_WAVE * 4) + lane_off));
+    };
+    int jn[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) jn[u] = idx_at(u);
+    for (int it0 = 0; it0 < iters; it0 += U) {
+        double px[U], py[U], pz[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) gather_q<LAYOUT>(a.pos, a.n, jn[u], px[u], py[u], pz[u]);
+        int jc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) jc[u] = jn[u];
+#pragma unroll
+        for (int u = 0; u < U; ++u) jn[u] = idx_at(it0 + U + u);
+        // keep the next indices' loads issued here, ahead of the arithmetic
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double tx = px[u] - qx, ty = py[u] - qy, tz = pz[u] - qz;
+            tx = fma(-rint(tx * a.inv_box[0]), a.box[0], tx);
+            ty = fma(-rint(ty * a.inv_box[1]), a.box[1], ty);
+            tz = fma(-rint(tz * a.inv_box[2]), a.box[2], tz);
+            const double r2 = r2_rounded(tx, ty, tz);
+            const bool m = (it0 + u < iters) && ((it0 + u) * G < lim) && (r2 < a.rc2);
+            double fs, sr6d;
+            if (PREC == LJ_FP64) {
+                const double ir2 = m ? recip(r2) : 0.0;
+                const double sr2 = a.sig2 * ir2;
+                const double sr6 = sr2 * sr2 * sr2;
+                fs = ir2 * (sr6 * fma(a.c48, sr6, -a.c24));
+                sr6d = sr6;
+            } else {
+                const float ir2 = m ? __builtin_amdgcn_rcpf((float)r2) : 0.0f;
+                const float sr2 = a.sig2f * ir2;
+                const float sr6 = sr2 * sr2 * sr2;
+                fs = (double)(ir2 * (sr6 * fmaf(a.c48f, sr6, -a.c24f)));
+                sr6d = (double)sr6;
+            }
+            // energy and virial from two sums: sum (sigma/r)^12 and sum (sigma/r)^6
+            sA = fma(sr6d, sr6d, sA);
+            sB += sr6d;
+            cnt += m ? 1 : 0;
+            fx = fma(-fs, tx, fx);
+            fy = fma(-fs, ty, fy);
+            fz = fma(-fs, tz, fz);
+            if (HALF && m) add_f<LAYOUT>(a.force, a.n, jc[u], fs * tx, fs * ty, fs * tz);
         }
-        w += fs * r2;
-        cnt += m ? 1.0 : 0.0;
-        fx -= fs * tx;
-        fy -= fs * ty;
-        fz -= fs * tz;
-        if (HALF && m) add_f<LAYOUT>(a.force, a.n, j, fs * tx, fs * ty, fs * tz);
     }
     // sum the row over its G lanes
 #pragma unroll
@@ -224,15 +287,16 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_force(ForceArgs a) {
         else
             store_f<LAYOUT>(a.force, a.n, i, fx, fy, fz);
     }
-    finish_reduction(a, e, w, cnt);
+    // per lane: 4 eps (A - B) and 24 eps (2A - B)
+    block_partials(a, a.c4 * (sA - sB), a.c24 * (2.0 * sA - sB), (double)cnt);
 }
 
-template <int G>
+template <int G, int U>
 lj_status launch_g(lj_ctx* ctx, const ForceArgs& a, bool half, int layout, int prec,
                    int64_t blocks) {
     dim3 grid((unsigned)blocks), block(LJ_BLOCK);
     hipStream_t s = ctx->stream;
-#define LJ_K(H, L, P) hipLaunchKernelGGL((k_force<G, H, L, P>), grid, block, 0, s, a)
+#define LJ_K(H, L, P) hipLaunchKernelGGL((k_force<G, H, L, P, U>), grid, block, 0, s, a)
     if (half) {
         if (layout == LJ_AOS4) {
             if (prec == LJ_FP64) LJ_K(true, LJ_AOS4, LJ_FP64); else LJ_K(true, LJ_AOS4, LJ_MIXED);
@@ -247,6 +311,9 @@ lj_status launch_g(lj_ctx* ctx, const ForceArgs& a, bool half, int layout, int p
         }
     }
 #undef LJ_K
+    LJ_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_force_reduce, dim3(1), dim3(1024), 0, s, (const double*)a.partials,
+                       blocks, a.scale, a.vc, a.energy, a.virial, a.npairs);
     LJ_HIP(hipGetLastError());
     return LJ_OK;
 }
@@ -304,14 +371,21 @@ lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, const lj_list* l,
     a.npairs = npairs;
     a.scale = half ? 1.0 : 0.5;
     lj_prof_scope prof(ctx, LJ_PROF_FORCE);
+    // entries in flight per lane: tuned value
+    const int u = ctx->tune[LJ_TUNE_FORCE_BATCH];
+#define LJ_U(G)                                                                          \
+    (u == 2 ? launch_g<G, 2>(ctx, a, half, p.layout, p.precision, blocks)                \
+            : u == 8 ? launch_g<G, 8>(ctx, a, half, p.layout, p.precision, blocks)       \
+                     : launch_g<G, 4>(ctx, a, half, p.layout, p.precision, blocks))
     switch (l->lanes) {
-        case 1: return launch_g<1>(ctx, a, half, p.layout, p.precision, blocks);
-        case 2: return launch_g<2>(ctx, a, half, p.layout, p.precision, blocks);
-        case 4: return launch_g<4>(ctx, a, half, p.layout, p.precision, blocks);
-        case 8: return launch_g<8>(ctx, a, half, p.layout, p.precision, blocks);
-        case 16: return launch_g<16>(ctx, a, half, p.layout, p.precision, blocks);
-        case 32: return launch_g<32>(ctx, a, half, p.layout, p.precision, blocks);
-        case 64: return launch_g<64>(ctx, a, half, p.layout, p.precision, blocks);
+        case 1: return LJ_U(1);
+        case 2: return LJ_U(2);
+        case 4: return LJ_U(4);
+        case 8: return LJ_U(8);
+        case 16: return LJ_U(16);
+        case 32: return LJ_U(32);
+        case 64: return LJ_U(64);
         default: return lj_fail(LJ_E_INVALID, "lanes must be 1, 2, 4, 8, 16, 32 or 64");
     }
+#undef LJ_U
 }

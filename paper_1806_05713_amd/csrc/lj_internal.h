@@ -61,6 +61,7 @@ struct lj_ctx {
     int64_t partials_cap;          // in blocks
     bool prof_on;
     std::vector<lj_prof_rec> prof;
+    int32_t tune[LJ_TUNE_N];       // tuning knobs (lj_tune_set)
 };
 
 // Records HIP events around a launch on the context's stream while the
@@ -85,6 +86,7 @@ struct lj_cells {
     int32_t* order;      // n
     double4* spos;       // n
     int32_t* block_sums; // scan workspace
+    bool counts_dirty;   // count[] may be non-zero (a build was interrupted)
 };
 
 struct lj_list {
@@ -100,6 +102,7 @@ struct lj_list {
     int32_t* row_atom;     // nslices * C
     int32_t* row_len;      // nslices * C
     int32_t* slice_iters;  // nslices
+    int32_t* slice_stats;  // 2 * nslices: longest row before clamping, entries
     int32_t* col;          // nslices * (cap / G) * 64
     lj_list_stats* stats;  // device
     lj_cells* cells;       // owned cell structure for in-place rebuilds (lazy)

@@ -32,8 +32,10 @@ LJ_AOS4, LJ_SOA = 0, 1
 # every entry point declared in include/lj.h
 EXPORTS = ["lj_create", "lj_destroy", "lj_set_stream", "lj_sync", "lj_build_cells",
            "lj_cells_info", "lj_cells_export", "lj_cells_free", "lj_build_neighbors",
-           "lj_update_neighbors", "lj_list_info", "lj_list_pairs", "lj_list_free", "lj_forces",
-           "lj_profile_begin", "lj_profile_end", "lj_last_error"]
+           "lj_update_neighbors", "lj_list_info", "lj_list_pairs", "lj_list_free",
+           "lj_list_device_view", "lj_forces",
+           "lj_profile_begin", "lj_profile_end", "lj_tune_set", "lj_tune_get", "lj_last_error"]
+LJ_TUNE_BUILD_LANES, LJ_TUNE_FORCE_BATCH, LJ_TUNE_CELL_DIV, LJ_TUNE_N = 0, 1, 2, 3
 LJ_PROF_CELLS, LJ_PROF_NEIGH, LJ_PROF_FORCE, LJ_PROF_OTHER, LJ_PROF_N = 0, 1, 2, 3, 4
 PROF_PHASES = ("cells", "neigh", "force", "other")
 
@@ -42,6 +44,12 @@ class LJError(RuntimeError):
     def __init__(self, status: int, what: str, text: str):
         self.status = status
         super().__init__(f"{what}: {STATUS_NAMES.get(status, status)}: {text}")
+
+
+class ListView(ctypes.Structure):
+    _fields_ = [("col", ctypes.c_void_p), ("row_atom", ctypes.c_void_p),
+                ("row_len", ctypes.c_void_p), ("slice_iters", ctypes.c_void_p),
+                ("nslices", ctypes.c_int64), ("lanes", ctypes.c_int32), ("cap", ctypes.c_int32)]
 
 
 class ListDesc(ctypes.Structure):
@@ -81,8 +89,11 @@ def load(path: str = LIB_PATH):
         "lj_list_info": ([_VP, ctypes.POINTER(ListDesc)]),
         "lj_profile_begin": ([_VP]),
         "lj_profile_end": ([_VP, _VP, _VP]),
+        "lj_tune_set": ([_VP, i32, i32]),
+        "lj_tune_get": ([_VP, i32, ctypes.POINTER(i32)]),
         "lj_list_pairs": ([_VP, _VP, i64, _VP, ctypes.POINTER(i64)]),
         "lj_list_free": ([_VP]),
+        "lj_list_device_view": ([_VP, ctypes.POINTER(ListView)]),
         "lj_forces": ([_VP, _VP, i64, i32, _D3, dbl, dbl, dbl, _VP, i32, _VP, _VP, _VP, _VP]),
     }
     for name, args in sig.items():
@@ -149,6 +160,14 @@ class Context:
     def sync(self):
         _check(load().lj_sync(self.h), "lj_sync")
 
+    def tune_set(self, knob: int, value: int):
+        _check(load().lj_tune_set(self.h, int(knob), int(value)), "lj_tune_set")
+
+    def tune_get(self, knob: int) -> int:
+        v = ctypes.c_int32()
+        _check(load().lj_tune_get(self.h, int(knob), ctypes.byref(v)), "lj_tune_get")
+        return v.value
+
     def profile_begin(self):
         _check(load().lj_profile_begin(self.h), "lj_profile_begin")
 
@@ -210,6 +229,11 @@ class NeighborList:
         d = ListDesc()
         _check(load().lj_list_info(self.h, ctypes.byref(d)), "lj_list_info")
         return d
+
+    def device_view(self) -> ListView:
+        v = ListView()
+        _check(load().lj_list_device_view(self.h, ctypes.byref(v)), "lj_list_device_view")
+        return v
 
     def pairs(self) -> np.ndarray:
         """(entries, 2) int32 array of the stored (i, j) entries."""

@@ -359,3 +359,59 @@ def test_cells_structure(lj, ctx):
         lo = np.array([cx, cy, cz]) * side
         p = s.pos[members]
         assert np.all(p >= lo - 1e-12) and np.all(p <= lo + side + 1e-12)
+
+
+@pytest.mark.parametrize("knob,value", [(0, 1), (0, 2), (0, 4), (1, 2), (1, 4), (1, 8),
+                                        (2, 1), (2, 2), (2, 3), (2, 4)])
+@pytest.mark.parametrize("kind", [0, 1])
+def test_tuning_knobs_do_not_change_results(lj, ctx, oracle, knob, value, kind):
+    """Every launch shape gives the exact pair set and the same forces."""
+    for name in ("lj4k", "fcc4-nc2"):
+        s = SYSTEMS[name]()
+        ref = reference(oracle, s)
+        pos = to_dev(s.pos, 0)
+        ctx.tune_set(knob, value)
+        try:
+            nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=kind)
+            lj.lj_update_neighbors(ctx, pos, s.box, nl)      # the in-place path too
+            ctx.sync()
+            ij = nl.pairs()
+            sel = ij if kind == 0 else ij[ij[:, 0] < ij[:, 1]]
+            assert np.array_equal(canon(sel), ref[0])
+            F, E, W, n = lj.lj_forces(ctx, pos, s.box, s.eps, s.sigma, s.rc, nl)
+            torch.cuda.synchronize()
+            check_forces(s, forces_to_np(F, 0), E.item(), W.item(), n.item(), ref)
+        finally:
+            ctx.tune_set(knob, 0)
+
+
+def test_update_neighbors_after_motion(lj, ctx, oracle):
+    """lj_update_neighbors on moved positions equals a fresh build."""
+    s = synth.lj4k()
+    rng = np.random.Generator(np.random.PCG64(44))
+    pos = to_dev(s.pos, 0)
+    nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=1)
+    moved = synth.wrap(s.pos + rng.uniform(-0.4, 0.4, size=s.pos.shape), s.box[0])
+    s2 = synth.System(pos=moved, box=s.box, rc=s.rc, skin=s.skin, name="moved")
+    ref = reference(oracle, s2)
+    pos2 = to_dev(moved, 0)
+    lj.lj_update_neighbors(ctx, pos2, s.box, nl)
+    ctx.sync()
+    ij = nl.pairs()
+    assert np.array_equal(canon(ij[ij[:, 0] < ij[:, 1]]), ref[0])
+    F, E, W, n = lj.lj_forces(ctx, pos2, s.box, 1.0, 1.0, s.rc, nl)
+    torch.cuda.synchronize()
+    check_forces(s2, forces_to_np(F, 0), E.item(), W.item(), n.item(), ref)
+
+
+def test_update_overflow_reported(lj, ctx):
+    """An in-place rebuild whose rows outgrow the capacity raises LJ_E_CAPACITY
+    at the next lj_sync (forced from the host by compressing the system)."""
+    s = synth.lj4k()
+    nl = lj.lj_build_neighbors(ctx, to_dev(s.pos, 0), s.box, s.rc, s.skin, kind=1)
+    dense = (s.pos * 0.5) + 0.25 * s.box[0]     # same atoms, 8x the density, same box
+    lj.lj_update_neighbors(ctx, to_dev(dense, 0), s.box, nl)
+    with pytest.raises(lj.LJError) as e:
+        ctx.sync()
+    assert e.value.status == lj.LJ_E_CAPACITY
+    ctx.sync()   # reported once: the next sync is clean
