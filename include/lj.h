@@ -211,6 +211,43 @@ LJ_API lj_status lj_forces(lj_ctx* ctx, const double* pos, int64_t n, int32_t la
                     const lj_list* list, int32_t precision, double* force, double* energy,
                     double* virial, int64_t* npairs);
 
+/* -------------------------------------------------------------- integrator */
+
+/* Velocity-Verlet NVE integration at unit mass around the force path.  One
+ * step, as in the oracle:
+ *   v += F dt/2;  x += v dt, wrapped to x - L floor(x/L) (a result equal to L
+ *   becomes 0);  if step % rebuild_every == 0 the list is rebuilt in place at
+ *   the new positions (lj_update_neighbors);  F = F(x) (lj_forces, in the
+ *   integrator's precision);  v += F dt/2.
+ * All state stays on the device and the integrator itself is FP64 whatever
+ * the force precision.  The caller's arrays are bound at creation (so that a
+ * captured HIP graph can replay them): pos, vel and force are device arrays
+ * of n records in `layout`; log is a device array of log_rows x 5 doubles
+ * that receives, for step s (row s, when s < log_rows): potential energy,
+ * kinetic energy (sum of v^2/2), virial, the largest displacement of any atom
+ * since the last list build, and the number of interacting pairs.  The list
+ * must belong to the same context and stay alive while the integrator is
+ * used.  *out is owned by the library until lj_nve_free. */
+typedef struct lj_nve lj_nve;
+LJ_API lj_status lj_nve_create(lj_ctx* ctx, double* pos, double* vel, double* force, int64_t n,
+                               int32_t layout, const double box[3], double eps, double sigma,
+                               double rc, int32_t precision, lj_list* list, double dt,
+                               int32_t rebuild_every, double* log, int64_t log_rows,
+                               lj_nve** out);
+/* Step 0: forces at the current positions and log row 0; resets the step
+ * count and the displacement record.  Asynchronous. */
+LJ_API lj_status lj_nve_init(lj_nve* nve);
+/* Advance nsteps steps.  use_graph != 0: whole rebuild cycles (rebuild_every
+ * steps ending with a rebuild) are captured once into a HIP graph and
+ * replayed; the remaining steps run as ordinary launches.  Requires the
+ * context's stream to be a created stream (not the null stream) when
+ * use_graph != 0.  Asynchronous; list overflow and bad coordinates are
+ * reported by lj_sync. */
+LJ_API lj_status lj_nve_run(lj_nve* nve, int32_t nsteps, int32_t use_graph);
+/* Steps taken since lj_nve_init (host counter). */
+LJ_API lj_status lj_nve_steps(const lj_nve* nve, int64_t* steps);
+LJ_API lj_status lj_nve_free(lj_nve* nve);
+
 /* ------------------------------------------------------------------ tuning */
 
 /* Launch-shape knobs of a context, set by the autotuner (or by hand).  They

@@ -20,7 +20,7 @@ INCLUDE = os.path.join(ROOT, "include")
 OUT = os.path.join(PKG, "liblj.so")
 BUILD = os.path.join(PKG, "_build")
 
-SOURCES = ["lj_api.hip", "lj_cells.hip", "lj_neigh.hip", "lj_force.hip"]
+SOURCES = ["lj_api.hip", "lj_cells.hip", "lj_neigh.hip", "lj_force.hip", "lj_nve.hip"]
 HEADERS = ["lj_internal.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

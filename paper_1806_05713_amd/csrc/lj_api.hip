@@ -454,6 +454,11 @@ extern "C" lj_status lj_build_neighbors(lj_ctx* ctx, const double* pos, int64_t 
     return LJ_OK;
 }
 
+lj_status lj_list_ensure_cells(lj_ctx* ctx, lj_list* l) {
+    if (l->cells) return LJ_OK;
+    return alloc_cells(l->n, l->box, internal_min_cell(ctx, l->rc + l->skin), &l->cells);
+}
+
 extern "C" lj_status lj_update_neighbors(lj_ctx* ctx, const double* pos, int64_t n,
                                          int32_t layout, const double box[3], lj_list* l) {
     lj_status st = check_common(ctx, pos, n, layout);
@@ -464,9 +469,7 @@ extern "C" lj_status lj_update_neighbors(lj_ctx* ctx, const double* pos, int64_t
     for (int d = 0; d < 3; ++d)
         if (l->box[d] != box[d]) return lj_fail(LJ_E_STALE, "list was built for another box");
     DeviceGuard guard(ctx->device);
-    if (!l->cells) {   // first update of a list built on caller-provided cells
-        if ((st = alloc_cells(n, box, internal_min_cell(ctx, l->rc + l->skin), &l->cells))) return st;
-    }
+    if ((st = lj_list_ensure_cells(ctx, l))) return st;   // lists built on caller cells
     if ((st = lj_launch_cells(ctx, pos, layout, l->cells))) return st;
     return lj_launch_neighbors(ctx, l->cells, l, l->rc + l->skin);
 }
@@ -558,6 +561,57 @@ extern "C" lj_status lj_list_device_view(const lj_list* l, lj_list_view* out) {
 
 extern "C" lj_status lj_list_free(lj_list* l) {
     list_release(l);
+    return LJ_OK;
+}
+
+// -------------------------------------------------------------- integrator
+
+extern "C" lj_status lj_nve_create(lj_ctx* ctx, double* pos, double* vel, double* force,
+                                   int64_t n, int32_t layout, const double box[3], double eps,
+                                   double sigma, double rc, int32_t precision, lj_list* list,
+                                   double dt, int32_t rebuild_every, double* log,
+                                   int64_t log_rows, lj_nve** out) {
+    lj_status st = check_common(ctx, pos, n, layout);
+    if (st) return st;
+    if (!vel || !force || !list || !out || !box)
+        return lj_fail(LJ_E_INVALID, "vel, force, list, box or out is NULL");
+    if (layout == LJ_AOS4 && (((uintptr_t)vel & 31u) || ((uintptr_t)force & 31u)))
+        return lj_fail(LJ_E_INVALID, "LJ_AOS4 arrays must be 32-byte aligned");
+    if (!finite_pos(eps) || !finite_pos(sigma) || !finite_pos(rc) || !finite_pos(dt))
+        return lj_fail(LJ_E_INVALID, "eps, sigma, rc and dt must be finite and > 0");
+    if (precision != LJ_FP64 && precision != LJ_MIXED)
+        return lj_fail(LJ_E_INVALID, "unknown precision");
+    if (rebuild_every < 1) return lj_fail(LJ_E_INVALID, "rebuild_every must be >= 1");
+    if (log_rows < 0 || (log_rows > 0 && !log)) return lj_fail(LJ_E_INVALID, "log is NULL");
+    if (list->n != n) return lj_fail(LJ_E_STALE, "list was built for another atom count");
+    for (int d = 0; d < 3; ++d)
+        if (list->box[d] != box[d]) return lj_fail(LJ_E_STALE, "list was built for another box");
+    if (rc > list->rc) return lj_fail(LJ_E_STALE, "rc is larger than the list's cutoff");
+    DeviceGuard guard(ctx->device);
+    if ((st = lj_list_ensure_cells(ctx, list))) return st;
+    return lj_nve_make(ctx, pos, vel, force, n, layout, box, eps, sigma, rc, precision, list, dt,
+                       rebuild_every, log, log_rows, out);
+}
+
+extern "C" lj_status lj_nve_init(lj_nve* nve) {
+    if (!nve) return lj_fail(LJ_E_INVALID, "integrator is NULL");
+    return lj_nve_start(nve);
+}
+
+extern "C" lj_status lj_nve_run(lj_nve* nve, int32_t nsteps, int32_t use_graph) {
+    if (!nve) return lj_fail(LJ_E_INVALID, "integrator is NULL");
+    if (nsteps < 0) return lj_fail(LJ_E_INVALID, "nsteps must be >= 0");
+    return lj_nve_advance(nve, nsteps, use_graph);
+}
+
+extern "C" lj_status lj_nve_steps(const lj_nve* nve, int64_t* steps) {
+    if (!nve || !steps) return lj_fail(LJ_E_INVALID, "integrator or steps is NULL");
+    *steps = lj_nve_step_count(nve);
+    return LJ_OK;
+}
+
+extern "C" lj_status lj_nve_free(lj_nve* nve) {
+    lj_nve_release(nve);
     return LJ_OK;
 }
 

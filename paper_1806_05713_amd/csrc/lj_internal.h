@@ -133,6 +133,16 @@ struct lj_force_params {
 lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, const lj_list* l,
                            const lj_force_params& p, double* force, double* energy,
                            double* virial, int64_t* npairs);
+// integrator (lj_nve.hip)
+lj_status lj_nve_make(lj_ctx* ctx, double* pos, double* vel, double* force, int64_t n,
+                      int32_t layout, const double box[3], double eps, double sigma, double rc,
+                      int32_t precision, lj_list* list, double dt, int32_t rebuild_every,
+                      double* log, int64_t log_rows, lj_nve** out);
+lj_status lj_nve_start(lj_nve* s);
+lj_status lj_nve_advance(lj_nve* s, int32_t nsteps, int32_t use_graph);
+void lj_nve_release(lj_nve* s);
+int64_t lj_nve_step_count(const lj_nve* s);
+lj_status lj_list_ensure_cells(lj_ctx* ctx, lj_list* l);
 // exclusive scan of m int32 values into out[0..m] (out[m] = total)
 lj_status lj_launch_scan(hipStream_t s, const int32_t* in, int32_t* out, int64_t m,
                          int32_t* work);

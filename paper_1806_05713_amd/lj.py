@@ -33,7 +33,8 @@ LJ_AOS4, LJ_SOA = 0, 1
 EXPORTS = ["lj_create", "lj_destroy", "lj_set_stream", "lj_sync", "lj_build_cells",
            "lj_cells_info", "lj_cells_export", "lj_cells_free", "lj_build_neighbors",
            "lj_update_neighbors", "lj_list_info", "lj_list_pairs", "lj_list_free",
-           "lj_list_device_view", "lj_forces",
+           "lj_list_device_view", "lj_forces", "lj_nve_create", "lj_nve_init", "lj_nve_run",
+           "lj_nve_steps", "lj_nve_free",
            "lj_profile_begin", "lj_profile_end", "lj_tune_set", "lj_tune_get", "lj_last_error"]
 LJ_TUNE_BUILD_LANES, LJ_TUNE_FORCE_BATCH, LJ_TUNE_CELL_DIV, LJ_TUNE_N = 0, 1, 2, 3
 LJ_PROF_CELLS, LJ_PROF_NEIGH, LJ_PROF_FORCE, LJ_PROF_OTHER, LJ_PROF_N = 0, 1, 2, 3, 4
@@ -95,6 +96,12 @@ def load(path: str = LIB_PATH):
         "lj_list_free": ([_VP]),
         "lj_list_device_view": ([_VP, ctypes.POINTER(ListView)]),
         "lj_forces": ([_VP, _VP, i64, i32, _D3, dbl, dbl, dbl, _VP, i32, _VP, _VP, _VP, _VP]),
+        "lj_nve_create": ([_VP, _VP, _VP, _VP, i64, i32, _D3, dbl, dbl, dbl, i32, _VP, dbl, i32,
+                           _VP, i64, PP]),
+        "lj_nve_init": ([_VP]),
+        "lj_nve_run": ([_VP, i32, i32]),
+        "lj_nve_steps": ([_VP, ctypes.POINTER(i64)]),
+        "lj_nve_free": ([_VP]),
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -301,6 +308,52 @@ def lj_forces(ctx: Context, pos, box, eps: float, sigma: float, rc: float,
                             float(rc), nlist.h, int(precision), _ptr(force), _ptr(out),
                             out.data_ptr() + 8, _ptr(cnt)), "lj_forces")
     return force, out[0:1], out[1:2], cnt
+
+
+class NVE:
+    """Velocity-Verlet integrator bound to device arrays pos, vel, force (same
+    layout) and a device log of log_rows x 5 doubles (lj_nve_create)."""
+
+    def __init__(self, ctx: Context, pos, vel, force, box, eps: float, sigma: float, rc: float,
+                 nlist: NeighborList, dt: float, rebuild_every: int = 10,
+                 precision: int = LJ_FP64, log_rows: int = 0):
+        import torch
+        n, layout = _pos_layout(pos)
+        for t in (vel, force):
+            if t.shape != pos.shape or t.dtype != pos.dtype:
+                raise ValueError("vel and force must match pos in shape and dtype")
+        self.ctx, self.pos, self.vel, self.force, self.nlist = ctx, pos, vel, force, nlist
+        self.log = torch.zeros((max(log_rows, 1), 5), dtype=torch.float64, device=pos.device)
+        h = _VP()
+        _check(load().lj_nve_create(ctx.h, _ptr(pos), _ptr(vel), _ptr(force), n, layout,
+                                    _box(box), float(eps), float(sigma), float(rc),
+                                    int(precision), nlist.h, float(dt), int(rebuild_every),
+                                    _ptr(self.log), int(log_rows), ctypes.byref(h)),
+               "lj_nve_create")
+        self.h = h
+
+    def init(self):
+        _check(load().lj_nve_init(self.h), "lj_nve_init")
+
+    def run(self, nsteps: int, use_graph: bool = False):
+        _check(load().lj_nve_run(self.h, int(nsteps), int(bool(use_graph))), "lj_nve_run")
+
+    @property
+    def steps(self) -> int:
+        v = ctypes.c_int64()
+        _check(load().lj_nve_steps(self.h, ctypes.byref(v)), "lj_nve_steps")
+        return v.value
+
+    def free(self):
+        if getattr(self, "h", None):
+            load().lj_nve_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def lj_last_error() -> str:
