@@ -99,8 +99,9 @@ typedef struct {
     int64_t entries;      /* stored (i, j) entries: pairs (half) or 2 x pairs (full) */
     int64_t slots;        /* entries including the padding of each wavefront slice */
     double rc, skin;      /* cutoff and skin the list was built for */
-    double box[3];        /* box it was built in */
-    int32_t nc[3];        /* cells per dimension used by the search */
+    double box[3];        /* box it was built in (system 0 of a batch) */
+    int32_t nc[3];        /* cells per dimension used by the search (system 0) */
+    int32_t nsys;         /* systems in the list (1 unless built as a batch) */
 } lj_list_desc;
 
 /* ---------------------------------------------------------------- context */
@@ -211,6 +212,30 @@ LJ_API lj_status lj_forces(lj_ctx* ctx, const double* pos, int64_t n, int32_t la
                     const lj_list* list, int32_t precision, double* force, double* energy,
                     double* virial, int64_t* npairs);
 
+/* ----------------------------------------------------------------- batches */
+
+/* Many independent systems of uneven size handled by every launch together
+ * (one launch per phase covers all systems).  System s owns the records
+ * [off_s, off_s + n[s]) of the caller's concatenated arrays, off_s = n[0] +
+ * ... + n[s-1], in the layout given (an LJ_SOA array is 3 x N for the total
+ * N).  Host arrays: n[nsys], box[3 * nsys], rc[nsys], eps[nsys], sigma[nsys].
+ * Each system has its own periodic box, cutoff and cells; the skin, list kind
+ * and lanes are shared.  The list's pairs (lj_list_pairs) carry record
+ * indices of the concatenated arrays; pairs never join two systems. */
+LJ_API lj_status lj_build_neighbors_batch(lj_ctx* ctx, const double* pos, int32_t layout,
+                                          int32_t nsys, const int64_t* n, const double* box,
+                                          const double* rc, double skin, int32_t kind,
+                                          int32_t lanes, lj_list** list);
+/* Forces over a batch list.  energy, virial: device arrays of nsys doubles;
+ * npairs: device array of nsys int64 or NULL. */
+LJ_API lj_status lj_forces_batch(lj_ctx* ctx, const double* pos, int32_t layout,
+                                 const lj_list* list, const double* eps, const double* sigma,
+                                 const double* rc, int32_t precision, double* force,
+                                 double* energy, double* virial, int64_t* npairs);
+/* Row statistics of system s of a list (synchronous). */
+LJ_API lj_status lj_list_sys_info(const lj_list* list, int32_t s, int64_t* n, int32_t* max_row,
+                                  int64_t* entries, int32_t* cap);
+
 /* -------------------------------------------------------------- integrator */
 
 /* Velocity-Verlet NVE integration at unit mass around the force path.  One
@@ -234,6 +259,13 @@ LJ_API lj_status lj_nve_create(lj_ctx* ctx, double* pos, double* vel, double* fo
                                double rc, int32_t precision, lj_list* list, double dt,
                                int32_t rebuild_every, double* log, int64_t log_rows,
                                lj_nve** out);
+/* The integrator of a batch list: eps, sigma, rc are host arrays of nsys
+ * values; the log holds log_rows x nsys x 5 doubles (row, system, quantity). */
+LJ_API lj_status lj_nve_create_batch(lj_ctx* ctx, double* pos, double* vel, double* force,
+                                     int32_t layout, const double* eps, const double* sigma,
+                                     const double* rc, int32_t precision, lj_list* list,
+                                     double dt, int32_t rebuild_every, double* log,
+                                     int64_t log_rows, lj_nve** out);
 /* Step 0: forces at the current positions and log row 0; resets the step
  * count and the displacement record.  Asynchronous. */
 LJ_API lj_status lj_nve_init(lj_nve* nve);

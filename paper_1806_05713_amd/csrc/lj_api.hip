@@ -134,12 +134,13 @@ lj_status read_status(lj_ctx* ctx, lj_dev_status* h) {
 }
 
 lj_status reset_status(lj_ctx* ctx) {
-    // flags only; the reduction arrival counter keeps its own state
-    return lj_launch_zero(ctx->stream, ctx->st, offsetof(lj_dev_status, done_blocks));
+    return lj_launch_zero(ctx->stream, ctx->st, sizeof(lj_dev_status));
 }
 
 void cells_release(lj_cells* c) {
     if (!c) return;
+    dfree(c->dsys);
+    dfree(c->atom_sys);
     dfree(c->count);
     dfree(c->cell_start);
     dfree(c->cid);
@@ -152,37 +153,84 @@ void cells_release(lj_cells* c) {
 
 void list_release(lj_list* l) {
     if (!l) return;
+    dfree(l->dsys);
+    dfree(l->slice_sys);
     dfree(l->row_atom);
     dfree(l->row_len);
     dfree(l->slice_iters);
     dfree(l->slice_stats);
     dfree(l->col);
     dfree(l->stats);
+    dfree(l->fc);
     cells_release(l->cells);
     delete l;
 }
 
-lj_status alloc_cells(int64_t n, const double* box, double min_cell, lj_cells** out) {
+template <typename T>
+lj_status upload(T* dst, const T* src, int64_t count, hipStream_t s) {
+    LJ_HIP(hipMemcpyAsync(dst, src, (size_t)count * sizeof(T), hipMemcpyHostToDevice, s));
+    LJ_HIP(hipStreamSynchronize(s));
+    return LJ_OK;
+}
+
+// Cell grid of one system: the largest cell count per dimension whose side
+// is >= min_cell.
+void sys_cells(lj_sys& sy, const double* box, double min_cell) {
+    sy.ncell = 1;
+    for (int d = 0; d < 3; ++d) {
+        sy.box[d] = box[d];
+        sy.half_box[d] = 0.5 * box[d];
+        sy.inv_box[d] = 1.0 / box[d];
+        sy.nc[d] = cells_for(box[d], min_cell);
+        sy.cs[d] = box[d] / sy.nc[d];
+        sy.inv_cs[d] = (double)sy.nc[d] / box[d];
+        sy.ncell *= sy.nc[d];
+    }
+}
+
+// Cells for nsys systems with n[s] atoms each; cells of side >= min_cell[s].
+lj_status alloc_cells(int nsys, const int64_t* n, const double* box, const double* min_cell,
+                      hipStream_t stream, lj_cells** out) {
     lj_cells* c = new (std::nothrow) lj_cells();
     if (!c) return lj_fail(LJ_E_NOMEM, "host allocation");
-    c->n = n;
-    c->ncell = 1;
+    c->nsys = nsys;
     c->counts_dirty = true;   // fresh allocation: cleared by the first build
-    for (int d = 0; d < 3; ++d) {
-        c->box[d] = box[d];
-        c->nc[d] = cells_for(box[d], min_cell);
-        c->cs[d] = box[d] / c->nc[d];
-        c->ncell *= c->nc[d];
+    c->hsys.assign(nsys, lj_sys());
+    int64_t atoms = 0, cells = 0;
+    for (int s = 0; s < nsys; ++s) {
+        lj_sys& sy = c->hsys[s];
+        sy.atom0 = atoms;
+        sy.n = n[s];
+        sy.cell0 = cells;
+        sys_cells(sy, box + 3 * s, min_cell[s]);
+        atoms += n[s];
+        cells += sy.ncell;
     }
-    if (c->ncell > (int64_t)16 * 1024 * 1024) {
+    c->n = atoms;
+    c->ncell = cells;
+    if (cells > (int64_t)16 * 1024 * 1024) {
         delete c;
-        return lj_fail(LJ_E_CAPACITY, "more than 16.7M cells: raise min_cell");
+        return lj_fail(LJ_E_CAPACITY, "more than 16.7M cells: raise the cell size");
     }
     lj_status st;
-    if ((st = dmalloc(&c->count, c->ncell)) || (st = dmalloc(&c->cell_start, c->ncell + 1)) ||
-        (st = dmalloc(&c->cid, n)) || (st = dmalloc(&c->order_tmp, n)) ||
-        (st = dmalloc(&c->order, n)) || (st = dmalloc(&c->spos, n)) ||
-        (st = dmalloc(&c->block_sums, lj_scan_workspace(c->ncell)))) {
+    if ((st = dmalloc(&c->dsys, nsys)) || (st = dmalloc(&c->count, cells)) ||
+        (st = dmalloc(&c->cell_start, cells + 1)) || (st = dmalloc(&c->cid, atoms)) ||
+        (st = dmalloc(&c->order_tmp, atoms)) || (st = dmalloc(&c->order, atoms)) ||
+        (st = dmalloc(&c->spos, atoms)) ||
+        (st = dmalloc(&c->block_sums, lj_scan_workspace(cells)))) {
+        cells_release(c);
+        return st;
+    }
+    if (nsys > 1) {
+        std::vector<int32_t> as((size_t)atoms);
+        for (int s = 0; s < nsys; ++s)
+            for (int64_t i = 0; i < n[s]; ++i) as[(size_t)(c->hsys[s].atom0 + i)] = s;
+        if ((st = dmalloc(&c->atom_sys, atoms)) || (st = upload(c->atom_sys, as.data(), atoms, stream))) {
+            cells_release(c);
+            return st;
+        }
+    }
+    if ((st = upload(c->dsys, c->hsys.data(), nsys, stream))) {
         cells_release(c);
         return st;
     }
@@ -196,14 +244,10 @@ lj_status fill_cells_sync(lj_ctx* ctx, const double* pos, int32_t layout, lj_cel
     if ((st = reset_status(ctx)) || (st = lj_launch_cells(ctx, pos, layout, c))) return st;
     lj_dev_status h;
     if ((st = read_status(ctx, &h))) return st;
-    if (h.flags & LJ_DEV_BAD_POSITION)
+    if (h.flags & LJ_DEV_BAD_POSITION) {
+        (void)reset_status(ctx);
         return lj_fail(LJ_E_POSITION, "a coordinate is non-finite or outside [0, box)");
-    return LJ_OK;
-}
-
-lj_status read_stats(const lj_list* l, hipStream_t s, lj_list_stats* h) {
-    LJ_HIP(hipMemcpyAsync(h, l->stats, sizeof(*h), hipMemcpyDeviceToHost, s));
-    LJ_HIP(hipStreamSynchronize(s));
+    }
     return LJ_OK;
 }
 
@@ -217,6 +261,186 @@ double internal_min_cell(const lj_ctx* ctx, double rs) {
     int k = ctx->tune[LJ_TUNE_CELL_DIV];
     if (k < 1 || k > 4) k = 2;
     return rs / k * (1.0 + 1e-11);
+}
+
+// List fields of a system derived from its cell grid and search length.
+void sys_list(lj_sys& sy, double rc, double skin) {
+    sy.rc_list = rc;
+    sy.skin = skin;
+    sy.rs = rc + skin;
+    sy.rs2 = sy.rs * sy.rs;
+    // delta: a few roundings of the largest coordinate, so that the cell range
+    // of a point never misses a cell holding a pair with r < rs
+    double L = sy.box[0] > sy.box[1] ? sy.box[0] : sy.box[1];
+    L = L > sy.box[2] ? L : sy.box[2];
+    const double delta = 16.0 * 2.220446049250313e-16 * (L + sy.rs);
+    const double rsd = sy.rs + delta;
+    // FP32 culling: inflated by a relative 1e-5, far above the FP32 rounding of
+    // the cell-relative quantities it is computed from
+    sy.rsd2f = (float)(rsd * rsd * (1.0 + 1e-5));
+    for (int d = 0; d < 3; ++d) {
+        sy.cs2f[d] = (float)(sy.cs[d] * sy.cs[d]);
+        sy.reach[d] = (int)ceil(rsd / sy.cs[d]);
+        sy.full[d] = (sy.nc[d] < 2 * sy.reach[d] + 2) ? 1 : 0;
+    }
+}
+
+// Slice ranges and slot offsets of every system for the current capacities.
+void layout_slices(lj_list* l) {
+    const int G = l->lanes, C = LJ_WAVE / G;
+    int64_t slices = 0, slots = 0;
+    for (lj_sys& sy : l->hsys) {
+        sy.slice0 = slices;
+        // whole 256-row blocks per system (a multiple of 4G slices)
+        const int64_t align = 4 * G;
+        sy.nslices = ((sy.n + C - 1) / C + align - 1) / align * align;
+        sy.col0 = slots;
+        slices += sy.nslices;
+        slots += sy.nslices * (int64_t)(sy.cap / G) * LJ_WAVE;
+    }
+    l->nslices = slices;
+    l->ncol = slots;
+}
+
+// Allocate the row and slice arrays of a list and fill slice_sys.
+lj_status alloc_rows(lj_list* l, hipStream_t stream) {
+    const int C = LJ_WAVE / l->lanes;
+    const int64_t rows = l->nslices * C;
+    lj_status st;
+    if ((st = dmalloc(&l->slice_sys, l->nslices)) || (st = dmalloc(&l->row_atom, rows)) ||
+        (st = dmalloc(&l->row_len, rows)) || (st = dmalloc(&l->slice_iters, l->nslices)) ||
+        (st = dmalloc(&l->slice_stats, 2 * l->nslices)) || (st = dmalloc(&l->stats, l->nsys)) ||
+        (st = dmalloc(&l->dsys, l->nsys)) || (st = dmalloc(&l->fc, l->nsys)))
+        return st;
+    std::vector<int32_t> ss((size_t)l->nslices);
+    for (int s = 0; s < l->nsys; ++s)
+        for (int64_t t = 0; t < l->hsys[s].nslices; ++t) ss[(size_t)(l->hsys[s].slice0 + t)] = s;
+    return upload(l->slice_sys, ss.data(), l->nslices, stream);
+}
+
+// The whole build: cells (given or own), then rows, growing each system's
+// capacity until every row fits.
+lj_status build_list(lj_ctx* ctx, const double* pos, int32_t layout, int nsys, const int64_t* n,
+                     const double* box, const double* rc, double skin, int32_t kind,
+                     int32_t lanes, const lj_cells* cells, lj_list** out) {
+    lj_list* l = new (std::nothrow) lj_list();
+    if (!l) return lj_fail(LJ_E_NOMEM, "host allocation");
+    l->nsys = nsys;
+    l->kind = kind;
+    l->lanes = lanes;
+    l->fc_valid = false;
+    lj_status st;
+    const lj_cells* c = cells;
+    if (!c) {
+        std::vector<double> mc((size_t)nsys);
+        for (int s = 0; s < nsys; ++s) mc[(size_t)s] = internal_min_cell(ctx, rc[s] + skin);
+        if ((st = alloc_cells(nsys, n, box, mc.data(), ctx->stream, &l->cells)) ||
+            (st = fill_cells_sync(ctx, pos, layout, l->cells))) {
+            list_release(l);
+            return st;
+        }
+        c = l->cells;
+    }
+    l->n = c->n;
+    l->hsys = c->hsys;
+    for (int s = 0; s < nsys; ++s) {
+        lj_sys& sy = l->hsys[(size_t)s];
+        sys_list(sy, rc[s], skin);
+        if (sy.reach[0] > 32 || sy.reach[1] > 32 || sy.reach[2] > 32) {
+            list_release(l);
+            return lj_fail(LJ_E_INVALID, "cells are smaller than (rc + skin) / 32");
+        }
+        // first guess of the row capacity: 1.25 x the neighbors within rs of
+        // an atom at the mean density, plus a margin; grown on overflow
+        const double vol = sy.box[0] * sy.box[1] * sy.box[2];
+        double expect = 4.18879020478639 * sy.rs * sy.rs * sy.rs * (double)sy.n / vol;
+        if (kind == LJ_LIST_HALF) expect *= 0.5;
+        int64_t cap = (int64_t)(1.25 * expect + 32.0);
+        if (cap > sy.n) cap = sy.n;
+        cap = ((cap + lanes - 1) / lanes) * lanes;
+        sy.cap = (int32_t)(cap < lanes ? lanes : cap);
+    }
+    layout_slices(l);
+    if ((st = alloc_rows(l, ctx->stream))) {
+        list_release(l);
+        return st;
+    }
+    std::vector<lj_list_stats> hs((size_t)nsys);
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        if (l->ncol > ((int64_t)1 << 31) - 1) {
+            st = lj_fail(LJ_E_CAPACITY, "list would exceed 2^31 slots");
+            break;
+        }
+        dfree(l->col);
+        l->col = nullptr;
+        if ((st = dmalloc(&l->col, l->ncol)) || (st = upload(l->dsys, l->hsys.data(), nsys, ctx->stream)))
+            break;
+        if ((st = lj_launch_neighbors(ctx, c, l))) break;
+        LJ_HIP(hipMemcpyAsync(hs.data(), l->stats, (size_t)nsys * sizeof(lj_list_stats),
+                              hipMemcpyDeviceToHost, ctx->stream));
+        LJ_HIP(hipStreamSynchronize(ctx->stream));
+        bool grown = false;
+        for (int s = 0; s < nsys; ++s) {
+            lj_sys& sy = l->hsys[(size_t)s];
+            if (hs[(size_t)s].max_row > sy.cap) {
+                int64_t cap = (int64_t)hs[(size_t)s].max_row + hs[(size_t)s].max_row / 16 + lanes;
+                cap = ((cap + lanes - 1) / lanes) * lanes;
+                sy.cap = (int32_t)cap;
+                grown = true;
+            }
+        }
+        if (!grown) {
+            st = LJ_OK;
+            break;
+        }
+        (void)reset_status(ctx);   // drop the overflow flag of the discarded build
+        layout_slices(l);
+        st = lj_fail(LJ_E_CAPACITY, "row capacity still too small after regrowth");
+    }
+    if (st) {
+        list_release(l);
+        return st;
+    }
+    // the force kernel's block partials must fit in the context
+    const int64_t blocks = lj_force_blocks(l->nslices);
+    if (blocks > ctx->partials_cap) {
+        double* p = nullptr;
+        if ((st = dmalloc(&p, 4 * blocks))) {
+            list_release(l);
+            return st;
+        }
+        (void)hipStreamSynchronize(ctx->stream);
+        dfree(ctx->partials);
+        ctx->partials = p;
+        ctx->partials_cap = blocks;
+    }
+    *out = l;
+    return LJ_OK;
+}
+
+// Force constants for the list's systems; uploaded when they change.
+lj_status set_fconst(lj_ctx* ctx, lj_list* l, const double* eps, const double* sigma,
+                     const double* rc) {
+    std::vector<lj_fconst> f((size_t)l->nsys);
+    for (int s = 0; s < l->nsys; ++s) f[(size_t)s] = lj_make_fconst(eps[s], sigma[s], rc[s]);
+    if (l->fc_valid && memcmp(f.data(), l->hfc.data(), f.size() * sizeof(lj_fconst)) == 0)
+        return LJ_OK;
+    l->hfc = f;
+    lj_status st = upload(l->fc, l->hfc.data(), l->nsys, ctx->stream);
+    if (st) return st;
+    l->fc_valid = true;
+    return LJ_OK;
+}
+
+lj_status check_params(int nsys, const double* eps, const double* sigma, const double* rc,
+                       const lj_list* l) {
+    for (int s = 0; s < nsys; ++s) {
+        if (!finite_pos(eps[s]) || !finite_pos(sigma[s]) || !finite_pos(rc[s]))
+            return lj_fail(LJ_E_INVALID, "eps, sigma and rc must be finite and > 0");
+        if (rc[s] > l->hsys[(size_t)s].rc_list)
+            return lj_fail(LJ_E_STALE, "rc is larger than the list's cutoff");
+    }
+    return LJ_OK;
 }
 
 }  // namespace
@@ -293,10 +517,11 @@ extern "C" lj_status lj_sync(lj_ctx* ctx) {
     }
     if (h.flags & LJ_DEV_BAD_POSITION)
         return lj_fail(LJ_E_POSITION, "a coordinate is non-finite or outside [0, box)");
-    if (h.flags & (LJ_DEV_ROW_OVERFLOW | LJ_DEV_CELL_OVERFLOW))
+    if (h.flags & LJ_DEV_ROW_OVERFLOW)
         return lj_fail(LJ_E_CAPACITY, "a list row exceeded its capacity");
     return LJ_OK;
 }
+
 
 // ------------------------------------------------------------------- cells
 
@@ -311,7 +536,7 @@ extern "C" lj_status lj_build_cells(lj_ctx* ctx, const double* pos, int64_t n, i
         if (!finite_pos(box[d])) return lj_fail(LJ_E_INVALID, "box lengths must be finite and > 0");
     DeviceGuard guard(ctx->device);
     lj_cells* c = nullptr;
-    if ((st = alloc_cells(n, box, min_cell, &c))) return st;
+    if ((st = alloc_cells(1, &n, box, &min_cell, ctx->stream, &c))) return st;
     if ((st = fill_cells_sync(ctx, pos, layout, c))) {
         cells_release(c);
         return st;
@@ -323,7 +548,7 @@ extern "C" lj_status lj_build_cells(lj_ctx* ctx, const double* pos, int64_t n, i
 extern "C" lj_status lj_cells_info(const lj_cells* c, int32_t nc[3], int64_t* n) {
     if (!c) return lj_fail(LJ_E_INVALID, "cells is NULL");
     if (nc)
-        for (int d = 0; d < 3; ++d) nc[d] = c->nc[d];
+        for (int d = 0; d < 3; ++d) nc[d] = c->hsys[0].nc[d];
     if (n) *n = c->n;
     return LJ_OK;
 }
@@ -362,101 +587,70 @@ extern "C" lj_status lj_build_neighbors(lj_ctx* ctx, const double* pos, int64_t 
     if (lanes == 0) lanes = default_lanes(kind);
     if (lanes < 1 || lanes > 64 || (lanes & (lanes - 1)))
         return lj_fail(LJ_E_INVALID, "lanes must be 1, 2, 4, 8, 16, 32 or 64");
-    const double rs = rc + skin;
-    if ((st = check_box(box, rs))) return st;
-    DeviceGuard guard(ctx->device);
-
+    if ((st = check_box(box, rc + skin))) return st;
     if (cells) {
-        if (cells->n != n) return lj_fail(LJ_E_STALE, "cells were built for another atom count");
-        for (int d = 0; d < 3; ++d) {
-            if (cells->box[d] != box[d]) return lj_fail(LJ_E_STALE, "cells were built for another box");
-            if (cells->nc[d] > 1 && cells->cs[d] * 16.0 < rs)
-                return lj_fail(LJ_E_INVALID, "cells are smaller than (rc + skin) / 16");
-        }
+        if (cells->nsys != 1 || cells->n != n)
+            return lj_fail(LJ_E_STALE, "cells were built for another atom count");
+        for (int d = 0; d < 3; ++d)
+            if (cells->hsys[0].box[d] != box[d])
+                return lj_fail(LJ_E_STALE, "cells were built for another box");
     }
-    lj_list* l = new (std::nothrow) lj_list();
-    if (!l) return lj_fail(LJ_E_NOMEM, "host allocation");
-    l->n = n;
-    l->kind = kind;
-    l->lanes = lanes;
-    l->rc = rc;
-    l->skin = skin;
-    for (int d = 0; d < 3; ++d) l->box[d] = box[d];
-    const lj_cells* c = cells;
-    if (!c) {
-        if ((st = alloc_cells(n, box, internal_min_cell(ctx, rs), &l->cells)) ||
-            (st = fill_cells_sync(ctx, pos, layout, l->cells))) {
-            list_release(l);
-            return st;
-        }
-        c = l->cells;
+    DeviceGuard guard(ctx->device);
+    return build_list(ctx, pos, layout, 1, &n, box, &rc, skin, kind, lanes, cells, list);
+}
+
+extern "C" lj_status lj_build_neighbors_batch(lj_ctx* ctx, const double* pos, int32_t layout,
+                                              int32_t nsys, const int64_t* n, const double* box,
+                                              const double* rc, double skin, int32_t kind,
+                                              int32_t lanes, lj_list** list) {
+    if (!ctx || !pos || !n || !box || !rc || !list)
+        return lj_fail(LJ_E_INVALID, "NULL argument");
+    if (nsys < 1) return lj_fail(LJ_E_INVALID, "nsys must be >= 1");
+    int64_t total = 0;
+    for (int s = 0; s < nsys; ++s) {
+        if (n[s] < 1) return lj_fail(LJ_E_INVALID, "every system needs at least one atom");
+        if (!finite_pos(rc[s])) return lj_fail(LJ_E_INVALID, "rc must be finite and > 0");
+        total += n[s];
     }
-    for (int d = 0; d < 3; ++d) l->nc[d] = c->nc[d];
-    const int C = LJ_WAVE / lanes;
-    // whole wavefronts of the build (up to 16 slices each, when it uses fewer
-    // lanes per row than the layout); trailing slices stay empty
-    l->nslices = ((n + C - 1) / C + 15) / 16 * 16;
-    // First guess of the row capacity: 1.25 x the neighbors within rs of an
-    // atom at the mean density, plus a margin; grown on overflow.
-    const double vol = box[0] * box[1] * box[2];
-    double expect = 4.18879020478639 * rs * rs * rs * (double)n / vol;   // (4/3) pi rs^3 rho
-    if (kind == LJ_LIST_HALF) expect *= 0.5;
-    int64_t cap = (int64_t)(1.25 * expect + 32.0);
-    if (cap > n) cap = n;
-    const int64_t slice_rows = l->nslices * C;
-    if ((st = dmalloc(&l->row_atom, slice_rows)) || (st = dmalloc(&l->row_len, slice_rows)) ||
-        (st = dmalloc(&l->slice_iters, l->nslices)) ||
-        (st = dmalloc(&l->slice_stats, 2 * l->nslices)) || (st = dmalloc(&l->stats, 1))) {
-        list_release(l);
-        return st;
-    }
-    for (int attempt = 0; attempt < 3; ++attempt) {
-        cap = ((cap + lanes - 1) / lanes) * lanes;
-        if (cap < lanes) cap = lanes;
-        if (l->nslices * cap * C > ((int64_t)1 << 40)) {
-            st = lj_fail(LJ_E_CAPACITY, "list would exceed 2^40 slots");
-            break;
-        }
-        l->cap = (int)cap;
-        dfree(l->col);
-        l->col = nullptr;
-        if ((st = dmalloc(&l->col, l->nslices * (cap / lanes) * LJ_WAVE))) break;
-        lj_list_stats h;
-        if ((st = lj_launch_neighbors(ctx, c, l, rs)) || (st = read_stats(l, ctx->stream, &h)))
-            break;
-        l->max_row = h.max_row;
-        l->entries = (int64_t)h.entries;
-        if (h.max_row <= cap) {
-            st = LJ_OK;
-            break;
-        }
-        cap = (int64_t)h.max_row + h.max_row / 16 + lanes;
-        st = lj_fail(LJ_E_CAPACITY, "row capacity still too small after regrowth");
-    }
-    if (st) {
-        list_release(l);
-        return st;
-    }
-    // the force kernel's block partials must fit in the context
-    const int64_t blocks = lj_force_blocks(l->nslices);
-    if (blocks > ctx->partials_cap) {
-        double* p = nullptr;
-        if ((st = dmalloc(&p, 4 * blocks))) {
-            list_release(l);
-            return st;
-        }
-        (void)hipStreamSynchronize(ctx->stream);
-        dfree(ctx->partials);
-        ctx->partials = p;
-        ctx->partials_cap = blocks;
-    }
-    *list = l;
-    return LJ_OK;
+    lj_status st = check_common(ctx, pos, total, layout);
+    if (st) return st;
+    if (!(skin >= 0.0) || !isfinite(skin)) return lj_fail(LJ_E_INVALID, "skin must be finite and >= 0");
+    if (kind != LJ_LIST_HALF && kind != LJ_LIST_FULL) return lj_fail(LJ_E_INVALID, "unknown list kind");
+    if (lanes == 0) lanes = default_lanes(kind);
+    if (lanes < 1 || lanes > 64 || (lanes & (lanes - 1)))
+        return lj_fail(LJ_E_INVALID, "lanes must be 1, 2, 4, 8, 16, 32 or 64");
+    for (int s = 0; s < nsys; ++s)
+        if ((st = check_box(box + 3 * s, rc[s] + skin))) return st;
+    DeviceGuard guard(ctx->device);
+    return build_list(ctx, pos, layout, nsys, n, box, rc, skin, kind, lanes, nullptr, list);
 }
 
 lj_status lj_list_ensure_cells(lj_ctx* ctx, lj_list* l) {
     if (l->cells) return LJ_OK;
-    return alloc_cells(l->n, l->box, internal_min_cell(ctx, l->rc + l->skin), &l->cells);
+    std::vector<int64_t> n((size_t)l->nsys);
+    std::vector<double> box((size_t)3 * l->nsys), mc((size_t)l->nsys);
+    for (int s = 0; s < l->nsys; ++s) {
+        const lj_sys& sy = l->hsys[(size_t)s];
+        n[(size_t)s] = sy.n;
+        for (int d = 0; d < 3; ++d) box[(size_t)(3 * s + d)] = sy.box[d];
+        mc[(size_t)s] = internal_min_cell(ctx, sy.rs);
+    }
+    lj_status st = alloc_cells(l->nsys, n.data(), box.data(), mc.data(), ctx->stream, &l->cells);
+    if (st) return st;
+    // the list's own cells may have another grid than the caller's: adopt it
+    for (int s = 0; s < l->nsys; ++s) {
+        lj_sys& sy = l->hsys[(size_t)s];
+        const lj_sys& cs = l->cells->hsys[(size_t)s];
+        sy.cell0 = cs.cell0;
+        sy.ncell = cs.ncell;
+        for (int d = 0; d < 3; ++d) {
+            sy.nc[d] = cs.nc[d];
+            sy.cs[d] = cs.cs[d];
+            sy.inv_cs[d] = cs.inv_cs[d];
+        }
+        sys_list(sy, sy.rc_list, sy.skin);
+    }
+    return upload(l->dsys, l->hsys.data(), l->nsys, ctx->stream);
 }
 
 extern "C" lj_status lj_update_neighbors(lj_ctx* ctx, const double* pos, int64_t n,
@@ -464,35 +658,57 @@ extern "C" lj_status lj_update_neighbors(lj_ctx* ctx, const double* pos, int64_t
     lj_status st = check_common(ctx, pos, n, layout);
     if (st) return st;
     if (!l) return lj_fail(LJ_E_INVALID, "list is NULL");
-    if (!box) return lj_fail(LJ_E_INVALID, "box is NULL");
     if (l->n != n) return lj_fail(LJ_E_STALE, "list was built for another atom count");
-    for (int d = 0; d < 3; ++d)
-        if (l->box[d] != box[d]) return lj_fail(LJ_E_STALE, "list was built for another box");
+    if (l->nsys == 1) {
+        if (!box) return lj_fail(LJ_E_INVALID, "box is NULL");
+        for (int d = 0; d < 3; ++d)
+            if (l->hsys[0].box[d] != box[d]) return lj_fail(LJ_E_STALE, "list was built for another box");
+    }
     DeviceGuard guard(ctx->device);
     if ((st = lj_list_ensure_cells(ctx, l))) return st;   // lists built on caller cells
     if ((st = lj_launch_cells(ctx, pos, layout, l->cells))) return st;
-    return lj_launch_neighbors(ctx, l->cells, l, l->rc + l->skin);
+    return lj_launch_neighbors(ctx, l->cells, l);
 }
 
 extern "C" lj_status lj_list_info(const lj_list* l, lj_list_desc* out) {
     if (!l || !out) return lj_fail(LJ_E_INVALID, "list or out is NULL");
-    lj_list_stats h;
+    std::vector<lj_list_stats> h((size_t)l->nsys);
     // the list may have been rebuilt on any stream of its context: wait for the device
     LJ_HIP(hipDeviceSynchronize());
-    LJ_HIP(hipMemcpy(&h, l->stats, sizeof(h), hipMemcpyDeviceToHost));
+    LJ_HIP(hipMemcpy(h.data(), l->stats, h.size() * sizeof(lj_list_stats), hipMemcpyDeviceToHost));
     out->n = l->n;
     out->kind = l->kind;
     out->lanes = l->lanes;
-    out->cap = l->cap;
-    out->max_row = h.max_row;
-    out->entries = (int64_t)h.entries;
-    out->slots = l->nslices * (int64_t)(l->cap / l->lanes) * LJ_WAVE;
-    out->rc = l->rc;
-    out->skin = l->skin;
-    for (int d = 0; d < 3; ++d) {
-        out->box[d] = l->box[d];
-        out->nc[d] = l->nc[d];
+    out->cap = 0;
+    out->max_row = 0;
+    out->entries = 0;
+    for (int s = 0; s < l->nsys; ++s) {
+        out->cap = out->cap > l->hsys[(size_t)s].cap ? out->cap : l->hsys[(size_t)s].cap;
+        out->max_row = out->max_row > h[(size_t)s].max_row ? out->max_row : h[(size_t)s].max_row;
+        out->entries += (int64_t)h[(size_t)s].entries;
     }
+    out->slots = l->ncol;
+    out->rc = l->hsys[0].rc_list;
+    out->skin = l->hsys[0].skin;
+    for (int d = 0; d < 3; ++d) {
+        out->box[d] = l->hsys[0].box[d];
+        out->nc[d] = l->hsys[0].nc[d];
+    }
+    out->nsys = l->nsys;
+    return LJ_OK;
+}
+
+extern "C" lj_status lj_list_sys_info(const lj_list* l, int32_t s, int64_t* n, int32_t* max_row,
+                                      int64_t* entries, int32_t* cap) {
+    if (!l) return lj_fail(LJ_E_INVALID, "list is NULL");
+    if (s < 0 || s >= l->nsys) return lj_fail(LJ_E_INVALID, "system index out of range");
+    lj_list_stats h;
+    LJ_HIP(hipDeviceSynchronize());
+    LJ_HIP(hipMemcpy(&h, l->stats + s, sizeof(h), hipMemcpyDeviceToHost));
+    if (n) *n = l->hsys[(size_t)s].n;
+    if (max_row) *max_row = h.max_row;
+    if (entries) *entries = (int64_t)h.entries;
+    if (cap) *cap = l->hsys[(size_t)s].cap;
     return LJ_OK;
 }
 
@@ -500,62 +716,49 @@ extern "C" lj_status lj_list_pairs(lj_ctx* ctx, const lj_list* l, int64_t cap, i
                                    int64_t* npairs) {
     if (!ctx || !l || !npairs) return lj_fail(LJ_E_INVALID, "context, list or npairs is NULL");
     DeviceGuard guard(ctx->device);
-    const int G = l->lanes, C = LJ_WAVE / G, S = l->cap / G;
+    const int G = l->lanes, C = LJ_WAVE / G;
     const int64_t rows = l->nslices * C;
-    const int64_t slots = l->nslices * (int64_t)S * LJ_WAVE;
-    int32_t* ra = (int32_t*)malloc((size_t)rows * sizeof(int32_t));
-    int32_t* rl = (int32_t*)malloc((size_t)rows * sizeof(int32_t));
-    int32_t* col = (int32_t*)malloc((size_t)slots * sizeof(int32_t));
-    lj_status st = LJ_OK;
-    if (!ra || !rl || !col) {
-        st = lj_fail(LJ_E_NOMEM, "host allocation");
-    } else {
-        hipError_t e = hipMemcpyAsync(ra, l->row_atom, rows * sizeof(int32_t),
-                                      hipMemcpyDeviceToHost, ctx->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(rl, l->row_len, rows * sizeof(int32_t), hipMemcpyDeviceToHost,
-                               ctx->stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(col, l->col, slots * sizeof(int32_t), hipMemcpyDeviceToHost,
-                               ctx->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-        if (e != hipSuccess) {
-            st = lj_hip_fail(e, "list copy");
-        } else {
-            int64_t total = 0;
-            for (int64_t r = 0; r < l->n; ++r) total += rl[r];
-            *npairs = total;
-            if (cap < total || (!ij && total > 0)) {
-                st = lj_fail(LJ_E_CAPACITY, "ij is too small for the list");
-            } else {
-                int64_t k = 0;
-                for (int64_t r = 0; r < l->n; ++r) {
-                    const int64_t s = r / C, c = r % C;
-                    for (int e2 = 0; e2 < rl[r]; ++e2) {
-                        const int64_t at = (s * S + e2 / G) * LJ_WAVE + c * G + (e2 % G);
-                        ij[2 * k] = ra[r];
-                        ij[2 * k + 1] = col[at];
-                        ++k;
-                    }
-                }
+    std::vector<int32_t> ra((size_t)rows), rl((size_t)rows), col((size_t)l->ncol);
+    LJ_HIP(hipMemcpyAsync(ra.data(), l->row_atom, rows * sizeof(int32_t), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    LJ_HIP(hipMemcpyAsync(rl.data(), l->row_len, rows * sizeof(int32_t), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    LJ_HIP(hipMemcpyAsync(col.data(), l->col, l->ncol * sizeof(int32_t), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    LJ_HIP(hipStreamSynchronize(ctx->stream));
+    int64_t total = 0;
+    for (const lj_sys& sy : l->hsys)
+        for (int64_t r = 0; r < sy.n; ++r) total += rl[(size_t)(sy.slice0 * C + r)];
+    *npairs = total;
+    if (cap < total || (!ij && total > 0))
+        return lj_fail(LJ_E_CAPACITY, "ij is too small for the list");
+    int64_t k = 0;
+    for (const lj_sys& sy : l->hsys) {
+        const int S = sy.cap / G;
+        for (int64_t r = 0; r < sy.n; ++r) {
+            const int64_t R = sy.slice0 * C + r;
+            const int64_t t = r / C, c = r % C;
+            for (int e = 0; e < rl[(size_t)R]; ++e) {
+                const int64_t at = sy.col0 + (t * S + e / G) * LJ_WAVE + c * G + (e % G);
+                ij[2 * k] = ra[(size_t)R];
+                ij[2 * k + 1] = col[(size_t)at];
+                ++k;
             }
         }
     }
-    free(ra);
-    free(rl);
-    free(col);
-    return st;
+    return LJ_OK;
 }
 
 extern "C" lj_status lj_list_device_view(const lj_list* l, lj_list_view* out) {
     if (!l || !out) return lj_fail(LJ_E_INVALID, "list or out is NULL");
+    if (l->nsys != 1) return lj_fail(LJ_E_INVALID, "the device view describes single-system lists");
     out->col = l->col;
     out->row_atom = l->row_atom;
     out->row_len = l->row_len;
     out->slice_iters = l->slice_iters;
     out->nslices = l->nslices;
     out->lanes = l->lanes;
-    out->cap = l->cap;
+    out->cap = l->hsys[0].cap;
     return LJ_OK;
 }
 
@@ -564,33 +767,99 @@ extern "C" lj_status lj_list_free(lj_list* l) {
     return LJ_OK;
 }
 
+// ------------------------------------------------------------------ forces
+
+extern "C" lj_status lj_forces(lj_ctx* ctx, const double* pos, int64_t n, int32_t layout,
+                               const double box[3], double eps, double sigma, double rc,
+                               const lj_list* list, int32_t precision, double* force,
+                               double* energy, double* virial, int64_t* npairs) {
+    lj_status st = check_common(ctx, pos, n, layout);
+    if (st) return st;
+    if (!list || !force || !energy || !virial)
+        return lj_fail(LJ_E_INVALID, "list, force, energy or virial is NULL");
+    if (layout == LJ_AOS4 && ((uintptr_t)force & 31u))
+        return lj_fail(LJ_E_INVALID, "LJ_AOS4 forces must be 32-byte aligned");
+    if (precision != LJ_FP64 && precision != LJ_MIXED)
+        return lj_fail(LJ_E_INVALID, "unknown precision");
+    if (!box) return lj_fail(LJ_E_INVALID, "box is NULL");
+    if (list->nsys != 1) return lj_fail(LJ_E_INVALID, "a batch list needs lj_forces_batch");
+    if (list->n != n) return lj_fail(LJ_E_STALE, "list was built for another atom count");
+    for (int d = 0; d < 3; ++d)
+        if (list->hsys[0].box[d] != box[d]) return lj_fail(LJ_E_STALE, "list was built for another box");
+    if ((st = check_params(1, &eps, &sigma, &rc, list))) return st;
+    DeviceGuard guard(ctx->device);
+    lj_list* l = const_cast<lj_list*>(list);
+    if ((st = set_fconst(ctx, l, &eps, &sigma, &rc))) return st;
+    return lj_launch_forces(ctx, pos, layout, precision, l, l->fc, force, energy, virial, npairs);
+}
+
+extern "C" lj_status lj_forces_batch(lj_ctx* ctx, const double* pos, int32_t layout,
+                                     const lj_list* list, const double* eps, const double* sigma,
+                                     const double* rc, int32_t precision, double* force,
+                                     double* energy, double* virial, int64_t* npairs) {
+    if (!list || !eps || !sigma || !rc || !force || !energy || !virial)
+        return lj_fail(LJ_E_INVALID, "NULL argument");
+    lj_status st = check_common(ctx, pos, list->n, layout);
+    if (st) return st;
+    if (layout == LJ_AOS4 && ((uintptr_t)force & 31u))
+        return lj_fail(LJ_E_INVALID, "LJ_AOS4 forces must be 32-byte aligned");
+    if (precision != LJ_FP64 && precision != LJ_MIXED)
+        return lj_fail(LJ_E_INVALID, "unknown precision");
+    if ((st = check_params(list->nsys, eps, sigma, rc, list))) return st;
+    DeviceGuard guard(ctx->device);
+    lj_list* l = const_cast<lj_list*>(list);
+    if ((st = set_fconst(ctx, l, eps, sigma, rc))) return st;
+    return lj_launch_forces(ctx, pos, layout, precision, l, l->fc, force, energy, virial, npairs);
+}
+
 // -------------------------------------------------------------- integrator
+
+static lj_status nve_create(lj_ctx* ctx, double* pos, double* vel, double* force, int32_t layout,
+                            const double* eps, const double* sigma, const double* rc,
+                            int32_t precision, lj_list* list, double dt, int32_t rebuild_every,
+                            double* log, int64_t log_rows, lj_nve** out) {
+    lj_status st = check_common(ctx, pos, list ? list->n : 0, layout);
+    if (st) return st;
+    if (!vel || !force || !list || !out)
+        return lj_fail(LJ_E_INVALID, "vel, force, list or out is NULL");
+    if (layout == LJ_AOS4 && (((uintptr_t)vel & 31u) || ((uintptr_t)force & 31u)))
+        return lj_fail(LJ_E_INVALID, "LJ_AOS4 arrays must be 32-byte aligned");
+    if (!finite_pos(dt)) return lj_fail(LJ_E_INVALID, "dt must be finite and > 0");
+    if (precision != LJ_FP64 && precision != LJ_MIXED)
+        return lj_fail(LJ_E_INVALID, "unknown precision");
+    if (rebuild_every < 1) return lj_fail(LJ_E_INVALID, "rebuild_every must be >= 1");
+    if (log_rows < 0 || (log_rows > 0 && !log)) return lj_fail(LJ_E_INVALID, "log is NULL");
+    if ((st = check_params(list->nsys, eps, sigma, rc, list))) return st;
+    DeviceGuard guard(ctx->device);
+    if ((st = lj_list_ensure_cells(ctx, list))) return st;
+    std::vector<lj_fconst> f((size_t)list->nsys);
+    for (int s = 0; s < list->nsys; ++s) f[(size_t)s] = lj_make_fconst(eps[s], sigma[s], rc[s]);
+    return lj_nve_make(ctx, pos, vel, force, layout, f.data(), precision, list, dt, rebuild_every,
+                       log, log_rows, out);
+}
 
 extern "C" lj_status lj_nve_create(lj_ctx* ctx, double* pos, double* vel, double* force,
                                    int64_t n, int32_t layout, const double box[3], double eps,
                                    double sigma, double rc, int32_t precision, lj_list* list,
                                    double dt, int32_t rebuild_every, double* log,
                                    int64_t log_rows, lj_nve** out) {
-    lj_status st = check_common(ctx, pos, n, layout);
-    if (st) return st;
-    if (!vel || !force || !list || !out || !box)
-        return lj_fail(LJ_E_INVALID, "vel, force, list, box or out is NULL");
-    if (layout == LJ_AOS4 && (((uintptr_t)vel & 31u) || ((uintptr_t)force & 31u)))
-        return lj_fail(LJ_E_INVALID, "LJ_AOS4 arrays must be 32-byte aligned");
-    if (!finite_pos(eps) || !finite_pos(sigma) || !finite_pos(rc) || !finite_pos(dt))
-        return lj_fail(LJ_E_INVALID, "eps, sigma, rc and dt must be finite and > 0");
-    if (precision != LJ_FP64 && precision != LJ_MIXED)
-        return lj_fail(LJ_E_INVALID, "unknown precision");
-    if (rebuild_every < 1) return lj_fail(LJ_E_INVALID, "rebuild_every must be >= 1");
-    if (log_rows < 0 || (log_rows > 0 && !log)) return lj_fail(LJ_E_INVALID, "log is NULL");
+    if (!list || !box) return lj_fail(LJ_E_INVALID, "list or box is NULL");
+    if (list->nsys != 1) return lj_fail(LJ_E_INVALID, "a batch list needs lj_nve_create_batch");
     if (list->n != n) return lj_fail(LJ_E_STALE, "list was built for another atom count");
     for (int d = 0; d < 3; ++d)
-        if (list->box[d] != box[d]) return lj_fail(LJ_E_STALE, "list was built for another box");
-    if (rc > list->rc) return lj_fail(LJ_E_STALE, "rc is larger than the list's cutoff");
-    DeviceGuard guard(ctx->device);
-    if ((st = lj_list_ensure_cells(ctx, list))) return st;
-    return lj_nve_make(ctx, pos, vel, force, n, layout, box, eps, sigma, rc, precision, list, dt,
-                       rebuild_every, log, log_rows, out);
+        if (list->hsys[0].box[d] != box[d]) return lj_fail(LJ_E_STALE, "list was built for another box");
+    return nve_create(ctx, pos, vel, force, layout, &eps, &sigma, &rc, precision, list, dt,
+                      rebuild_every, log, log_rows, out);
+}
+
+extern "C" lj_status lj_nve_create_batch(lj_ctx* ctx, double* pos, double* vel, double* force,
+                                         int32_t layout, const double* eps, const double* sigma,
+                                         const double* rc, int32_t precision, lj_list* list,
+                                         double dt, int32_t rebuild_every, double* log,
+                                         int64_t log_rows, lj_nve** out) {
+    if (!list || !eps || !sigma || !rc) return lj_fail(LJ_E_INVALID, "NULL argument");
+    return nve_create(ctx, pos, vel, force, layout, eps, sigma, rc, precision, list, dt,
+                      rebuild_every, log, log_rows, out);
 }
 
 extern "C" lj_status lj_nve_init(lj_nve* nve) {
@@ -673,33 +942,3 @@ extern "C" lj_status lj_profile_end(lj_ctx* ctx, double* ms, int64_t* launches) 
 }
 
 // ------------------------------------------------------------------ forces
-
-extern "C" lj_status lj_forces(lj_ctx* ctx, const double* pos, int64_t n, int32_t layout,
-                               const double box[3], double eps, double sigma, double rc,
-                               const lj_list* list, int32_t precision, double* force,
-                               double* energy, double* virial, int64_t* npairs) {
-    lj_status st = check_common(ctx, pos, n, layout);
-    if (st) return st;
-    if (!list || !force || !energy || !virial)
-        return lj_fail(LJ_E_INVALID, "list, force, energy or virial is NULL");
-    if (layout == LJ_AOS4 && ((uintptr_t)force & 31u))
-        return lj_fail(LJ_E_INVALID, "LJ_AOS4 forces must be 32-byte aligned");
-    if (!finite_pos(eps) || !finite_pos(sigma) || !finite_pos(rc))
-        return lj_fail(LJ_E_INVALID, "eps, sigma and rc must be finite and > 0");
-    if (precision != LJ_FP64 && precision != LJ_MIXED)
-        return lj_fail(LJ_E_INVALID, "unknown precision");
-    if (!box) return lj_fail(LJ_E_INVALID, "box is NULL");
-    if (list->n != n) return lj_fail(LJ_E_STALE, "list was built for another atom count");
-    for (int d = 0; d < 3; ++d)
-        if (list->box[d] != box[d]) return lj_fail(LJ_E_STALE, "list was built for another box");
-    if (rc > list->rc) return lj_fail(LJ_E_STALE, "rc is larger than the list's cutoff");
-    DeviceGuard guard(ctx->device);
-    lj_force_params p;
-    for (int d = 0; d < 3; ++d) p.box[d] = box[d];
-    p.eps = eps;
-    p.sigma = sigma;
-    p.rc = rc;
-    p.layout = layout;
-    p.precision = precision;
-    return lj_launch_forces(ctx, pos, list, p, force, energy, virial, npairs);
-}

@@ -36,11 +36,10 @@ __device__ __forceinline__ void load_xyz(const double* __restrict__ pos, int64_t
 
 struct BinArgs {
     const double* pos;
-    int64_t n;
+    int64_t n;                 // atoms over all systems
     int layout;
-    double box[3];
-    double inv_cs[3];
-    int nc[3];
+    const lj_sys* sys;
+    const int32_t* atom_sys;   // system of each atom, or NULL for a single system
     int32_t* cid;
     int32_t* count;
     lj_dev_status* st;
@@ -49,20 +48,21 @@ struct BinArgs {
 __global__ __launch_bounds__(LJ_BLOCK) void k_bin(BinArgs a) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= a.n) return;
+    const lj_sys& sy = a.sys[a.atom_sys ? a.atom_sys[i] : 0];
     double x, y, z;
     load_xyz(a.pos, a.n, a.layout, i, x, y, z);
     const bool ok = isfinite(x) && isfinite(y) && isfinite(z) && x >= 0.0 && y >= 0.0 &&
-                    z >= 0.0 && x < a.box[0] && y < a.box[1] && z < a.box[2];
-    int c = 0;
+                    z >= 0.0 && x < sy.box[0] && y < sy.box[1] && z < sy.box[2];
+    int64_t c = sy.cell0;
     if (ok) {
-        const int cx = lj_cell_coord(x, a.inv_cs[0], a.nc[0]);
-        const int cy = lj_cell_coord(y, a.inv_cs[1], a.nc[1]);
-        const int cz = lj_cell_coord(z, a.inv_cs[2], a.nc[2]);
-        c = (cz * a.nc[1] + cy) * a.nc[0] + cx;
+        const int cx = lj_cell_coord(x, sy.inv_cs[0], sy.nc[0]);
+        const int cy = lj_cell_coord(y, sy.inv_cs[1], sy.nc[1]);
+        const int cz = lj_cell_coord(z, sy.inv_cs[2], sy.nc[2]);
+        c += ((int64_t)cz * sy.nc[1] + cy) * sy.nc[0] + cx;
     } else {
         atomicOr(&a.st->flags, LJ_DEV_BAD_POSITION);
     }
-    a.cid[i] = c;
+    a.cid[i] = (int32_t)c;
     atomicAdd(&a.count[c], 1);
 }
 
@@ -278,11 +278,8 @@ lj_status lj_launch_cells(lj_ctx* ctx, const double* pos, int layout, lj_cells* 
     a.pos = pos;
     a.n = c->n;
     a.layout = layout;
-    for (int d = 0; d < 3; ++d) {
-        a.box[d] = c->box[d];
-        a.inv_cs[d] = (double)c->nc[d] / c->box[d];
-        a.nc[d] = c->nc[d];
-    }
+    a.sys = c->dsys;
+    a.atom_sys = c->atom_sys;
     a.cid = c->cid;
     a.count = c->count;
     a.st = ctx->st;

@@ -28,23 +28,16 @@ namespace {
 struct ForceArgs {
     const double* pos;
     double* force;
-    int64_t n;
+    int64_t n;               // atoms over all systems (SoA stride)
     int64_t nslices;
-    int S;                   // slots per row in G-wide steps (cap / G)
-    double box[3], inv_box[3];
-    double rc2;
-    double sig2, c4, c24, c48, vc;   // sigma^2, 4 eps, 24 eps, 48 eps, V(rc)
-    float sig2f, c4f, c24f, c48f;
+    const lj_sys* sys;
+    const lj_fconst* fc;
+    const int32_t* slice_sys;
     const int32_t* row_atom;
     const int32_t* row_len;
     const int32_t* slice_iters;
     const int32_t* col;
-    double* partials;        // 4 doubles per block
-    lj_dev_status* st;
-    double* energy;
-    double* virial;
-    int64_t* npairs;
-    double scale;
+    double* partials;        // 4 doubles per (logical) block
 };
 
 __device__ __forceinline__ double r2_rounded(double x, double y, double z) {
@@ -103,7 +96,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 // order.  No atomics: a device-scope atomic must stay coherent across the
 // eight per-XCD L2 caches and is resolved beyond them, so thousands of blocks
 // hitting one counter serialise.
-__device__ void block_partials(const ForceArgs& a, double e, double w, double cnt) {
+__device__ void block_partials(const ForceArgs& a, int64_t blk, double e, double w, double cnt) {
     __shared__ double red[LJ_WAVES_PER_BLOCK][3];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     e = wave_sum(e);
@@ -122,22 +115,26 @@ __device__ void block_partials(const ForceArgs& a, double e, double w, double cn
             bw += red[k][1];
             bc += red[k][2];
         }
-        double* p = a.partials + 4 * (int64_t)blockIdx.x;
+        double* p = a.partials + 4 * blk;
         p[0] = be;
         p[1] = bw;
         p[2] = bc;
     }
 }
 
-// One block: thread t sums partials t, t + 1024, ... then a fixed tree.
+// One block per system: thread t sums the system's block partials t, t + 1024,
+// ... then a fixed tree; writes the system's energy, virial and pair count.
 __global__ __launch_bounds__(1024) void k_force_reduce(const double* __restrict__ partials,
-                                                       int64_t nblocks, double scale, double vc,
-                                                       double* energy, double* virial,
-                                                       int64_t* npairs) {
+                                                       const lj_sys* sys, const lj_fconst* fc,
+                                                       double scale, double* energy,
+                                                       double* virial, int64_t* npairs) {
     __shared__ double red[16][3];
+    const lj_sys& sy = sys[blockIdx.x];
+    const int64_t b0 = sy.slice0 / LJ_WAVES_PER_BLOCK;
+    const int64_t b1 = (sy.slice0 + sy.nslices) / LJ_WAVES_PER_BLOCK;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double se = 0.0, sw = 0.0, sc = 0.0;
-    for (int64_t b = threadIdx.x; b < nblocks; b += 1024) {
+    for (int64_t b = b0 + threadIdx.x; b < b1; b += 1024) {
         se += partials[4 * b + 0];
         sw += partials[4 * b + 1];
         sc += partials[4 * b + 2];
@@ -158,9 +155,9 @@ __global__ __launch_bounds__(1024) void k_force_reduce(const double* __restrict_
             tw += red[k][1];
             tc += red[k][2];
         }
-        *energy = scale * (te - tc * vc);
-        *virial = scale * tw;
-        if (npairs) *npairs = (int64_t)(scale * tc + 0.5);
+        energy[blockIdx.x] = scale * (te - tc * fc[blockIdx.x].vc);
+        virial[blockIdx.x] = scale * tw;
+        if (npairs) npairs[blockIdx.x] = (int64_t)(scale * tc + 0.5);
     }
 }
 
@@ -200,22 +197,27 @@ template <int G, bool HALF, int LAYOUT, int PREC, int U>
 __global__ __launch_bounds__(LJ_BLOCK) void k_force(ForceArgs a) {
     constexpr int C = LJ_WAVE / G;
     const int lane = threadIdx.x & (LJ_WAVE - 1);
+    const int64_t blk = lj_xcd_block(blockIdx.x, gridDim.x);
     const int slice = __builtin_amdgcn_readfirstlane(
-        (int)lj_xcd_block(blockIdx.x, gridDim.x) * LJ_WAVES_PER_BLOCK + (threadIdx.x >> 6));
-    const bool slice_ok = slice < a.nslices;
-    const int iters = slice_ok ? __builtin_amdgcn_readfirstlane(a.slice_iters[slice]) : 0;
+        (int)blk * LJ_WAVES_PER_BLOCK + (threadIdx.x >> 6));
+    // a block's four slices belong to one system (systems own whole 256-row blocks)
+    const int sid = __builtin_amdgcn_readfirstlane(a.slice_sys[blk * LJ_WAVES_PER_BLOCK]);
+    const lj_sys& sy = a.sys[sid];
+    const lj_fconst& fc = a.fc[sid];
+    const int iters = __builtin_amdgcn_readfirstlane(a.slice_iters[slice]);
     const int c = lane / G, g = lane % G;
-    const int r = slice * C + c;
-    int i = 0, lim = 0;
-    if (slice_ok) {
-        i = a.row_atom[r];
-        lim = a.row_len[r] - g;   // entry it*G + g is inside the row iff it*G < lim
-    }
+    const int64_t r = (int64_t)slice * C + c;
+    const int i = a.row_atom[r];
+    const int lim = a.row_len[r] - g;   // entry it*G + g is inside the row iff it*G < lim
+    const bool row_ok = (r - sy.slice0 * C) < sy.n;
+    const double bx = sy.box[0], by = sy.box[1], bz = sy.box[2];
+    const double ibx = sy.inv_box[0], iby = sy.inv_box[1], ibz = sy.inv_box[2];
+    const double rc2 = fc.rc2;
     double qx, qy, qz;
     gather_q<LAYOUT>(a.pos, a.n, i, qx, qy, qz);
 
-    const char* colbase =
-        reinterpret_cast<const char*>(a.col + (int64_t)(slice_ok ? slice : 0) * a.S * LJ_WAVE);
+    const char* colbase = reinterpret_cast<const char*>(
+        a.col + sy.col0 + (int64_t)(slice - sy.slice0) * (sy.cap / G) * LJ_WAVE);
     const uint32_t lane_off = (uint32_t)lane * 4u;
     double fx = 0.0, fy = 0.0, fz = 0.0, sA = 0.0, sB = 0.0;
     int cnt = 0;
@@ -245,23 +247,23 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_force(ForceArgs a) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             double tx = px[u] - qx, ty = py[u] - qy, tz = pz[u] - qz;
-            tx = fma(-rint(tx * a.inv_box[0]), a.box[0], tx);
-            ty = fma(-rint(ty * a.inv_box[1]), a.box[1], ty);
-            tz = fma(-rint(tz * a.inv_box[2]), a.box[2], tz);
+            tx = fma(-rint(tx * ibx), bx, tx);
+            ty = fma(-rint(ty * iby), by, ty);
+            tz = fma(-rint(tz * ibz), bz, tz);
             const double r2 = r2_rounded(tx, ty, tz);
-            const bool m = (it0 + u < iters) && ((it0 + u) * G < lim) && (r2 < a.rc2);
+            const bool m = (it0 + u < iters) && ((it0 + u) * G < lim) && (r2 < rc2);
             double fs, sr6d;
             if (PREC == LJ_FP64) {
                 const double ir2 = m ? recip(r2) : 0.0;
-                const double sr2 = a.sig2 * ir2;
+                const double sr2 = fc.sig2 * ir2;
                 const double sr6 = sr2 * sr2 * sr2;
-                fs = ir2 * (sr6 * fma(a.c48, sr6, -a.c24));
+                fs = ir2 * (sr6 * fma(fc.c48, sr6, -fc.c24));
                 sr6d = sr6;
             } else {
                 const float ir2 = m ? __builtin_amdgcn_rcpf((float)r2) : 0.0f;
-                const float sr2 = a.sig2f * ir2;
+                const float sr2 = fc.sig2f * ir2;
                 const float sr6 = sr2 * sr2 * sr2;
-                fs = (double)(ir2 * (sr6 * fmaf(a.c48f, sr6, -a.c24f)));
+                fs = (double)(ir2 * (sr6 * fmaf(fc.c48f, sr6, -fc.c24f)));
                 sr6d = (double)sr6;
             }
             // energy and virial from two sums: sum (sigma/r)^12 and sum (sigma/r)^6
@@ -281,14 +283,14 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_force(ForceArgs a) {
         fy += __shfl_xor(fy, d, LJ_WAVE);
         fz += __shfl_xor(fz, d, LJ_WAVE);
     }
-    if (slice_ok && g == 0 && r < a.n) {
+    if (g == 0 && row_ok) {
         if (HALF)
             add_f<LAYOUT>(a.force, a.n, i, fx, fy, fz);
         else
             store_f<LAYOUT>(a.force, a.n, i, fx, fy, fz);
     }
     // per lane: 4 eps (A - B) and 24 eps (2A - B)
-    block_partials(a, a.c4 * (sA - sB), a.c24 * (2.0 * sA - sB), (double)cnt);
+    block_partials(a, blk, fc.c4 * (sA - sB), fc.c24 * (2.0 * sA - sB), (double)cnt);
 }
 
 template <int G, int U>
@@ -312,9 +314,6 @@ lj_status launch_g(lj_ctx* ctx, const ForceArgs& a, bool half, int layout, int p
     }
 #undef LJ_K
     LJ_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_force_reduce, dim3(1), dim3(1024), 0, s, (const double*)a.partials,
-                       blocks, a.scale, a.vc, a.energy, a.virial, a.npairs);
-    LJ_HIP(hipGetLastError());
     return LJ_OK;
 }
 
@@ -324,15 +323,32 @@ int64_t lj_force_blocks(int64_t nslices) {
     return (nslices + LJ_WAVES_PER_BLOCK - 1) / LJ_WAVES_PER_BLOCK;
 }
 
-lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, const lj_list* l,
-                           const lj_force_params& p, double* force, double* energy,
+lj_fconst lj_make_fconst(double eps, double sigma, double rc) {
+    lj_fconst f;
+    f.rc2 = rc * rc;
+    f.sig2 = sigma * sigma;
+    f.c4 = 4.0 * eps;
+    f.c24 = 24.0 * eps;
+    f.c48 = 48.0 * eps;
+    const double s2 = f.sig2 / f.rc2;
+    const double s6 = s2 * s2 * s2;
+    f.vc = 4.0 * eps * s6 * (s6 - 1.0);
+    f.sig2f = (float)f.sig2;
+    f.c4f = (float)f.c4;
+    f.c24f = (float)f.c24;
+    f.c48f = (float)f.c48;
+    return f;
+}
+
+lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int precision,
+                           const lj_list* l, const lj_fconst* fc, double* force, double* energy,
                            double* virial, int64_t* npairs) {
     const int64_t blocks = lj_force_blocks(l->nslices);
     if (blocks > ctx->partials_cap) return lj_fail(LJ_E_INVALID, "context partials too small");
     const bool half = l->kind == LJ_LIST_HALF;
     if (half) {
         lj_prof_scope prof(ctx, LJ_PROF_OTHER);
-        const int64_t bytes = (int64_t)sizeof(double) * (p.layout == LJ_AOS4 ? 4 : 3) * l->n;
+        const int64_t bytes = (int64_t)sizeof(double) * (layout == LJ_AOS4 ? 4 : 3) * l->n;
         lj_status st = lj_launch_zero(ctx->stream, force, bytes);
         if (st) return st;
     }
@@ -341,51 +357,40 @@ lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, const lj_list* l,
     a.force = force;
     a.n = l->n;
     a.nslices = l->nslices;
-    a.S = l->cap / l->lanes;
-    for (int d = 0; d < 3; ++d) {
-        a.box[d] = p.box[d];
-        a.inv_box[d] = 1.0 / p.box[d];
-    }
-    a.rc2 = p.rc * p.rc;
-    a.sig2 = p.sigma * p.sigma;
-    a.c4 = 4.0 * p.eps;
-    a.c24 = 24.0 * p.eps;
-    a.c48 = 48.0 * p.eps;
-    {
-        const double s2 = a.sig2 / a.rc2;
-        const double s6 = s2 * s2 * s2;
-        a.vc = 4.0 * p.eps * s6 * (s6 - 1.0);
-    }
-    a.sig2f = (float)a.sig2;
-    a.c4f = (float)a.c4;
-    a.c24f = (float)a.c24;
-    a.c48f = (float)a.c48;
+    a.sys = l->dsys;
+    a.fc = fc;
+    a.slice_sys = l->slice_sys;
     a.row_atom = l->row_atom;
     a.row_len = l->row_len;
     a.slice_iters = l->slice_iters;
     a.col = l->col;
     a.partials = ctx->partials;
-    a.st = ctx->st;
-    a.energy = energy;
-    a.virial = virial;
-    a.npairs = npairs;
-    a.scale = half ? 1.0 : 0.5;
-    lj_prof_scope prof(ctx, LJ_PROF_FORCE);
-    // entries in flight per lane: tuned value
-    const int u = ctx->tune[LJ_TUNE_FORCE_BATCH];
-#define LJ_U(G)                                                                          \
-    (u == 2 ? launch_g<G, 2>(ctx, a, half, p.layout, p.precision, blocks)                \
-            : u == 8 ? launch_g<G, 8>(ctx, a, half, p.layout, p.precision, blocks)       \
-                     : launch_g<G, 4>(ctx, a, half, p.layout, p.precision, blocks))
-    switch (l->lanes) {
-        case 1: return LJ_U(1);
-        case 2: return LJ_U(2);
-        case 4: return LJ_U(4);
-        case 8: return LJ_U(8);
-        case 16: return LJ_U(16);
-        case 32: return LJ_U(32);
-        case 64: return LJ_U(64);
-        default: return lj_fail(LJ_E_INVALID, "lanes must be 1, 2, 4, 8, 16, 32 or 64");
-    }
+    lj_status st;
+    {
+        lj_prof_scope prof(ctx, LJ_PROF_FORCE);
+        // entries in flight per lane: tuned value
+        const int u = ctx->tune[LJ_TUNE_FORCE_BATCH];
+#define LJ_U(G)                                                                      \
+    (u == 2 ? launch_g<G, 2>(ctx, a, half, layout, precision, blocks)                \
+            : u == 8 ? launch_g<G, 8>(ctx, a, half, layout, precision, blocks)       \
+                     : launch_g<G, 4>(ctx, a, half, layout, precision, blocks))
+        switch (l->lanes) {
+            case 1: st = LJ_U(1); break;
+            case 2: st = LJ_U(2); break;
+            case 4: st = LJ_U(4); break;
+            case 8: st = LJ_U(8); break;
+            case 16: st = LJ_U(16); break;
+            case 32: st = LJ_U(32); break;
+            case 64: st = LJ_U(64); break;
+            default: return lj_fail(LJ_E_INVALID, "lanes must be 1, 2, 4, 8, 16, 32 or 64");
+        }
 #undef LJ_U
+    }
+    if (st) return st;
+    lj_prof_scope prof(ctx, LJ_PROF_OTHER);
+    hipLaunchKernelGGL(k_force_reduce, dim3((unsigned)l->nsys), dim3(1024), 0, ctx->stream,
+                       (const double*)ctx->partials, (const lj_sys*)l->dsys, fc,
+                       half ? 1.0 : 0.5, energy, virial, npairs);
+    LJ_HIP(hipGetLastError());
+    return LJ_OK;
 }

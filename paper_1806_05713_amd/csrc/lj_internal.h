@@ -1,19 +1,29 @@
 // lj_internal.h -- internal structures and launchers of the gfx950 LJ library.
 //
-// Data layout in HBM (per system):
-//   positions     caller's array: n x double4 (x, y, z, pad) or SoA 3 x n
-//   cells         count[ncell], cell_start[ncell + 1], cid[n] (cell of atom),
-//                 order[n] (cell-sorted rank -> atom), spos[n] (cell-sorted
-//                 double4 (x, y, z, atom index as a double))
-//   list          wavefront-sliced rows: rows are the atoms in cell order; a
-//                 wavefront of 64 lanes serves C = 64 / G rows with G lanes
-//                 each; entry k of row c of slice s is stored at
-//                   col[(s * (cap / G) + k / G) * 64 + c * G + k % G]
-//                 so that one 64-lane load fetches 256 contiguous bytes.
-//                 row_atom[r], row_len[r] per row, slice_iters[s] = the
-//                 longest row of the slice in G-wide steps.  Slots past a
-//                 row's length (up to its slice's length) hold the row's own
-//                 atom so that every gather stays in bounds.
+// Every kernel works on a batch of independent systems (a single system is a
+// batch of one).  System s owns records [atom0, atom0 + n) of the caller's
+// concatenated position/velocity/force arrays and is described on the device
+// by an lj_sys record.
+//
+// Data layout in HBM:
+//   positions  caller's array: records of double4 (x, y, z, pad) or SoA 3 x N
+//   cells      count[ncell], cell_start[ncell + 1] over the concatenated cell
+//              grids (system s owns cells [cell0, cell0 + ncell_s)), cid[N]
+//              (cell of atom), order[N] (cell-sorted rank -> atom), spos[N]
+//              (cell-sorted double4 (x, y, z, atom index as a double)).  The
+//              ranks of system s are [atom0, atom0 + n).
+//   list       wavefront-sliced rows: a slice is C = 64 / G rows served by one
+//              wavefront with G lanes per row; rows are the atoms in cell
+//              order.  System s owns slices [slice0, slice0 + nslices), a
+//              multiple of 4G (whole 256-row blocks), so that every
+//              wavefront, 4-slice force block and 256-row block belongs to one
+//              system; row r of the system is rank atom0 + r - slice0 * C.
+//              Entry k of row c of slice t (local index t - slice0) is at
+//                col[col0 + (t_local * (cap / G) + k / G) * 64 + c * G + k % G]
+//              so one 64-lane load fetches 256 contiguous bytes.  row_atom,
+//              row_len per row; slice_iters[t] = the slice's longest row in
+//              G-wide steps; slots past a row's length (up to its slice's
+//              length) hold the row's own atom so every gather stays in bounds.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,24 +39,47 @@
 #define LJ_WAVES_PER_BLOCK (LJ_BLOCK / LJ_WAVE)
 #define LJ_NXCD 8
 
+// One system of a batch (device and host copies).
+struct lj_sys {
+    // atoms
+    int64_t atom0, n;
+    // cells
+    int64_t cell0, ncell;
+    int32_t nc[3];
+    int32_t reach[3];      // cells within rs + delta of a point lie within +-reach
+    int32_t full[3];       // 1: fewer than 2 reach + 2 cells -> the dimension is scanned whole
+    int32_t pad0;
+    double box[3], half_box[3], inv_box[3], inv_cs[3], cs[3];
+    float cs2f[3];         // cell side^2 (FP32, culling only)
+    float rsd2f;           // (rs + delta)^2, inflated (culling only)
+    double rs, rc_list, skin, rs2;
+    // list
+    int64_t slice0, nslices, col0;
+    int32_t cap;           // slots per row, a multiple of the lanes per row
+    int32_t pad1;
+};
+
+// Force constants of one system.
+struct lj_fconst {
+    double rc2, sig2, c4, c24, c48, vc;   // rc^2, sigma^2, 4 eps, 24 eps, 48 eps, V(rc)
+    float sig2f, c4f, c24f, c48f;
+};
+
 // Device status words of a context.
 struct lj_dev_status {
     int32_t flags;                 // LJ_DEV_* bits raised by kernels
     int32_t pad0;
     unsigned long long pad1;
-    unsigned int done_blocks;      // arrival counter of the last-block reductions
-    unsigned int pad;
 };
+#define LJ_DEV_BAD_POSITION 1
+#define LJ_DEV_ROW_OVERFLOW 2
 
-// Row statistics of a list, written by its latest build on the device.
+// Row statistics of one system of a list, written by its latest build.
 struct lj_list_stats {
     int32_t max_row;               // longest row (before clamping to the capacity)
     int32_t pad;
     unsigned long long entries;    // entries stored
 };
-#define LJ_DEV_BAD_POSITION 1
-#define LJ_DEV_ROW_OVERFLOW 2
-#define LJ_DEV_CELL_OVERFLOW 4
 
 struct lj_prof_rec {
     int phase;
@@ -74,38 +107,41 @@ struct lj_prof_scope {
 };
 
 struct lj_cells {
-    int64_t n;
-    int nc[3];
-    double cs[3];
-    double box[3];
-    int64_t ncell;
-    int32_t* count;      // ncell
-    int32_t* cell_start; // ncell + 1
-    int32_t* cid;        // n
-    int32_t* order_tmp;  // n (unsorted within cells)
-    int32_t* order;      // n
-    double4* spos;       // n
-    int32_t* block_sums; // scan workspace
-    bool counts_dirty;   // count[] may be non-zero (a build was interrupted)
+    int nsys;
+    int64_t n;                     // atoms over all systems
+    int64_t ncell;                 // cells over all systems
+    std::vector<lj_sys> hsys;      // cell fields valid
+    lj_sys* dsys;                  // device copy
+    int32_t* atom_sys;             // device, system of each atom (NULL for one system)
+    int32_t* count;                // ncell
+    int32_t* cell_start;           // ncell + 1
+    int32_t* cid;                  // n
+    int32_t* order_tmp;            // n (unsorted within cells)
+    int32_t* order;                // n
+    double4* spos;                 // n
+    int32_t* block_sums;           // scan workspace
+    bool counts_dirty;             // count[] may be non-zero (a build was interrupted)
 };
 
 struct lj_list {
+    int nsys;
     int64_t n;
     int kind;
-    int lanes;         // G
-    int cap;           // multiple of G
-    int max_row;
-    int64_t entries;
-    int64_t nslices;
-    double rc, skin, box[3];
-    int nc[3];
-    int32_t* row_atom;     // nslices * C
-    int32_t* row_len;      // nslices * C
-    int32_t* slice_iters;  // nslices
-    int32_t* slice_stats;  // 2 * nslices: longest row before clamping, entries
-    int32_t* col;          // nslices * (cap / G) * 64
-    lj_list_stats* stats;  // device
-    lj_cells* cells;       // owned cell structure for in-place rebuilds (lazy)
+    int lanes;                     // G
+    int64_t nslices, ncol;
+    std::vector<lj_sys> hsys;      // all fields valid
+    lj_sys* dsys;                  // device copy
+    int32_t* slice_sys;            // nslices: system of each slice
+    int32_t* row_atom;             // nslices * C
+    int32_t* row_len;              // nslices * C
+    int32_t* slice_iters;          // nslices
+    int32_t* slice_stats;          // 2 * nslices: longest row before clamping, entries
+    int32_t* col;                  // ncol
+    lj_list_stats* stats;          // device, nsys
+    lj_fconst* fc;                 // device, nsys: force constants of the last lj_forces*
+    std::vector<lj_fconst> hfc;    // host copy of fc
+    bool fc_valid;
+    lj_cells* cells;               // owned cell structure for in-place rebuilds (lazy)
 };
 
 // ---------------------------------------------------------------- errors
@@ -121,23 +157,17 @@ lj_status lj_hip_fail(hipError_t e, const char* what);
 // cells (lj_cells.hip)
 lj_status lj_launch_cells(lj_ctx* ctx, const double* pos, int layout, lj_cells* c);
 int64_t lj_scan_workspace(int64_t m);
-// neighbor list (lj_neigh.hip)
-lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l, double rs);
+// neighbor list (lj_neigh.hip): rebuild every system of l from cells c
+lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l);
+// forces (lj_force.hip): per-system energy, virial, pair count
 int64_t lj_force_blocks(int64_t nslices);
-// forces (lj_force.hip)
-struct lj_force_params {
-    double box[3];
-    double eps, sigma, rc;
-    int layout, precision;
-};
-lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, const lj_list* l,
-                           const lj_force_params& p, double* force, double* energy,
+lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int precision,
+                           const lj_list* l, const lj_fconst* fc, double* force, double* energy,
                            double* virial, int64_t* npairs);
 // integrator (lj_nve.hip)
-lj_status lj_nve_make(lj_ctx* ctx, double* pos, double* vel, double* force, int64_t n,
-                      int32_t layout, const double box[3], double eps, double sigma, double rc,
-                      int32_t precision, lj_list* list, double dt, int32_t rebuild_every,
-                      double* log, int64_t log_rows, lj_nve** out);
+lj_status lj_nve_make(lj_ctx* ctx, double* pos, double* vel, double* force, int32_t layout,
+                      const lj_fconst* hfc, int32_t precision, lj_list* list, double dt,
+                      int32_t rebuild_every, double* log, int64_t log_rows, lj_nve** out);
 lj_status lj_nve_start(lj_nve* s);
 lj_status lj_nve_advance(lj_nve* s, int32_t nsteps, int32_t use_graph);
 void lj_nve_release(lj_nve* s);
@@ -147,6 +177,8 @@ lj_status lj_list_ensure_cells(lj_ctx* ctx, lj_list* l);
 lj_status lj_launch_scan(hipStream_t s, const int32_t* in, int32_t* out, int64_t m,
                          int32_t* work);
 lj_status lj_launch_zero(hipStream_t s, void* p, int64_t bytes);
+// host: force constants of one system
+lj_fconst lj_make_fconst(double eps, double sigma, double rc);
 
 // ------------------------------------------------------- device helpers
 // Logical block index that gives each XCD a contiguous range of blocks

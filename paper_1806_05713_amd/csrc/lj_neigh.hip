@@ -29,18 +29,9 @@
 namespace {
 
 struct NeighArgs {
-    int64_t n;
-    int64_t nslices;
-    int nc[3];
-    int reach[3];          // R: cells within rs + delta of a point lie within +-R
-    int full[3];           // 1: the dimension has < 2R + 2 cells -> scan all of them
-    double box[3];
-    double half_box[3];
-    double inv_cs[3];
-    float cs2f[3];         // cell side^2 (FP32, culling only)
-    float rsd2f;           // (rs + delta)^2, inflated (culling only)
-    double rs2;
-    int cap;
+    int64_t nslices;       // over all systems
+    const lj_sys* sys;
+    const int32_t* slice_sys;
     const int32_t* cell_start;
     const double4* spos;
     int32_t* row_atom;
@@ -77,31 +68,40 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
         (int)lj_xcd_block(blockIdx.x, gridDim.x) * LJ_WAVES_PER_BLOCK + (threadIdx.x >> 6));
     const int64_t row0 = (int64_t)wv * CB;
     if (row0 >= a.nslices * C) return;   // whole wavefront leaves together
+    // the wavefront's rows belong to one system (systems own whole 256-row blocks)
+    const int sid = __builtin_amdgcn_readfirstlane(a.slice_sys[row0 / C]);
+    const lj_sys& sy = a.sys[sid];
     const int cb = lane / GB, g = lane % GB;
-    const int64_t r = row0 + cb;
-    const int r32 = (int)r;
-    const bool row_ok = r < a.n;
-    const int64_t slice = r / C;
-    const int c = (int)(r % C);
-    const int S = a.cap / G;
-    const int64_t slot0 = slice * (int64_t)S * LJ_WAVE + c * G;
+    const int64_t R = row0 + cb;                 // row of the list
+    const int64_t lr = R - sy.slice0 * C;        // row within the system
+    const bool row_ok = lr < sy.n;
+    const int64_t rank = sy.atom0 + (row_ok ? lr : 0);
+    const int r32 = (int)rank;
+    const int64_t slice = R / C;
+    const int c = (int)(R % C);
+    const int S = sy.cap / G;
+    const int cap = sy.cap;
+    const double rs2 = sy.rs2;
+    const int64_t slot0 = sy.col0 + (slice - sy.slice0) * (int64_t)S * LJ_WAVE + c * G;
     int32_t* __restrict__ col = a.col;
+    const int32_t* __restrict__ cell_start = a.cell_start + sy.cell0;
 
-    const double4 qi = a.spos[row_ok ? r : 0];
+    const double4 qi = a.spos[rank];
     const int32_t self = (int32_t)qi.w;
-    const int nx = a.nc[0], ny = a.nc[1], nz = a.nc[2];
+    const int nx = sy.nc[0], ny = sy.nc[1], nz = sy.nc[2];
     // cell of the atom and its fractional position in the cell (FP32, culling only)
-    const int cx = lj_cell_coord(qi.x, a.inv_cs[0], nx);
-    const int cy = lj_cell_coord(qi.y, a.inv_cs[1], ny);
-    const int cz = lj_cell_coord(qi.z, a.inv_cs[2], nz);
-    const float fx = (float)(qi.x * a.inv_cs[0] - cx);
-    const float fy = (float)(qi.y * a.inv_cs[1] - cy);
-    const float fz = (float)(qi.z * a.inv_cs[2] - cz);
+    const int cx = lj_cell_coord(qi.x, sy.inv_cs[0], nx);
+    const int cy = lj_cell_coord(qi.y, sy.inv_cs[1], ny);
+    const int cz = lj_cell_coord(qi.z, sy.inv_cs[2], nz);
+    const float fx = (float)(qi.x * sy.inv_cs[0] - cx);
+    const float fy = (float)(qi.y * sy.inv_cs[1] - cy);
+    const float fz = (float)(qi.z * sy.inv_cs[2] - cz);
 
-    const bool fullx = ANYFULL && a.full[0], fully = ANYFULL && a.full[1],
-               fullz = ANYFULL && a.full[2];
-    const int Rx = a.reach[0], Ry = fully ? 0 : a.reach[1], Rz = fullz ? 0 : a.reach[2];
+    const bool fullx = ANYFULL && sy.full[0], fully = ANYFULL && sy.full[1],
+               fullz = ANYFULL && sy.full[2];
+    const int Rx = sy.reach[0], Ry = fully ? 0 : sy.reach[1], Rz = fullz ? 0 : sy.reach[2];
     const int ky_n = fully ? ny : 2 * Ry + 1, kz_n = fullz ? nz : 2 * Rz + 1;
+    const float rsd2f = sy.rsd2f;
 
     // the ballot bits of this row's GB lanes
     const uint64_t grp = (GB == LJ_WAVE) ? ~0ull : (((1ull << (GB & 63)) - 1ull) << (cb * GB));
@@ -114,9 +114,9 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
             reinterpret_cast<const char*>(a.spos) + (uint32_t)s * 32u);
         double tx = qj.x - qi.x, ty = qj.y - qi.y, tz = qj.z - qi.z;
         if (ANYFULL) {
-            tx = fullx ? nearest(tx, a.box[0], a.half_box[0]) : (shifted_x ? tx + shx : tx);
-            ty = fully ? nearest(ty, a.box[1], a.half_box[1]) : ty + shy;
-            tz = fullz ? nearest(tz, a.box[2], a.half_box[2]) : tz + shz;
+            tx = fullx ? nearest(tx, sy.box[0], sy.half_box[0]) : (shifted_x ? tx + shx : tx);
+            ty = fully ? nearest(ty, sy.box[1], sy.half_box[1]) : ty + shy;
+            tz = fullz ? nearest(tz, sy.box[2], sy.half_box[2]) : tz + shz;
         } else {
             if (shifted_x) tx = tx + shx;
             ty = ty + shy;
@@ -127,7 +127,7 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
         if (HALF) own = ((s > r32) != (((s + r32) & 1) != 0));
         jv = (int32_t)qj.w;
         // bitwise: no short-circuit branch around the loads
-        return (s != r32) & own & (r2 < a.rs2);
+        return (s != r32) & own & (r2 < rs2);
     };
     auto put = [&](uint32_t k, int32_t jv) {
         col[slot0 + (int64_t)(k / (uint32_t)G) * LJ_WAVE + (k % (uint32_t)G)] = jv;
@@ -141,18 +141,18 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
                 const bool p0 = test(s0 + f, shx, shy, shz, shifted_x, j0);
                 const bool p1 = test(s0 + f + 1, shx, shy, shz, shifted_x, j1);
                 if (p0) {
-                    if (cnt < a.cap) put((uint32_t)cnt, j0);
+                    if (cnt < cap) put((uint32_t)cnt, j0);
                     ++cnt;
                 }
                 if (p1) {
-                    if (cnt < a.cap) put((uint32_t)cnt, j1);
+                    if (cnt < cap) put((uint32_t)cnt, j1);
                     ++cnt;
                 }
             }
             if (f < m) {
                 int32_t j0;
                 if (test(s0 + f, shx, shy, shz, shifted_x, j0)) {
-                    if (cnt < a.cap) put((uint32_t)cnt, j0);
+                    if (cnt < cap) put((uint32_t)cnt, j0);
                     ++cnt;
                 }
             }
@@ -167,7 +167,7 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
                                bhi = (uint32_t)(ball >> 32) & grp_hi;
                 const int k = cnt + (int)__builtin_amdgcn_mbcnt_hi(
                                         bhi, __builtin_amdgcn_mbcnt_lo(blo, 0u));
-                if (pass && k < a.cap) put((uint32_t)k, jv);
+                if (pass && k < cap) put((uint32_t)k, jv);
                 cnt += __builtin_popcount(blo) + __builtin_popcount(bhi);
             }
         }
@@ -185,10 +185,10 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
             wz = cz + oz;
             if (wz < 0) {
                 wz += nz;
-                shz = -a.box[2];
+                shz = -sy.box[2];
             } else if (wz >= nz) {
                 wz -= nz;
-                shz = a.box[2];
+                shz = sy.box[2];
             }
         }
         for (int ky = 0; ky < ky_n; ++ky) {
@@ -203,23 +203,23 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
                 wy = cy + oy;
                 if (wy < 0) {
                     wy += ny;
-                    shy = -a.box[1];
+                    shy = -sy.box[1];
                 } else if (wy >= ny) {
                     wy -= ny;
-                    shy = a.box[1];
+                    shy = sy.box[1];
                 }
             }
             // squared distance from the atom to this cell row (FP32, conservative)
-            const float d2 = fmaf(gy * gy, a.cs2f[1], gz * gz * a.cs2f[2]);
+            const float d2 = fmaf(gy * gy, sy.cs2f[1], gz * gz * sy.cs2f[2]);
             int xa0 = 0, xa1 = 0, xb0 = 0, xb1 = 0;
             double shb = 0.0;
-            if (row_ok && d2 < a.rsd2f) {
+            if (row_ok && d2 < rsd2f) {
                 if (fullx) {
                     xa1 = nx;
                 } else {
                     // chord half-width in cells, inflated
                     const float wcell =
-                        __builtin_amdgcn_sqrtf((a.rsd2f - d2) / a.cs2f[0]) * 1.00001f + 1e-5f;
+                        __builtin_amdgcn_sqrtf((rsd2f - d2) / sy.cs2f[0]) * 1.00001f + 1e-5f;
                     int u0 = cx + (int)floorf(fx - wcell);
                     int u1 = cx + (int)floorf(fx + wcell);
                     u0 = max(u0, cx - Rx);
@@ -227,13 +227,13 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
                     if (u0 < 0) {           // [u0, -1] wraps to the top with -L
                         xb0 = u0 + nx;
                         xb1 = nx;
-                        shb = -a.box[0];
+                        shb = -sy.box[0];
                         xa1 = u1 + 1;
                     } else if (u1 >= nx) {  // [nx, u1] wraps to the bottom with +L
                         xa0 = u0;
                         xa1 = nx;
                         xb1 = u1 - nx + 1;
-                        shb = a.box[0];
+                        shb = sy.box[0];
                     } else {
                         xa0 = u0;
                         xa1 = u1 + 1;
@@ -243,19 +243,19 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
             const int rowbase = (wz * ny + wy) * nx;
             int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
             if (xa1 > xa0) {
-                a0 = a.cell_start[rowbase + xa0];
-                a1 = a.cell_start[rowbase + xa1];
+                a0 = cell_start[rowbase + xa0];
+                a1 = cell_start[rowbase + xa1];
             }
             if (xb1 > xb0) {
-                b0 = a.cell_start[rowbase + xb0];
-                b1 = a.cell_start[rowbase + xb1];
+                b0 = cell_start[rowbase + xb0];
+                b1 = cell_start[rowbase + xb1];
             }
             scan(a0, a1 - a0, 0.0, shy, shz, false);
             scan(b0, b1 - b0, shb, shy, shz, true);
         }
     }
 
-    const int len = cnt < a.cap ? cnt : a.cap;
+    const int len = cnt < cap ? cnt : cap;
     // longest row and entries of each slice (its SL lanes; no atomics)
     int mx = len, over = cnt, tot = (g == 0) ? len : 0;
 #pragma unroll
@@ -268,8 +268,8 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
     // pad the row up to the slice length with the row's own atom
     for (int k = len + g; k < iters * G; k += GB) put((uint32_t)k, self);
     if (g == 0) {
-        a.row_atom[r] = row_ok ? self : 0;
-        a.row_len[r] = row_ok ? len : 0;
+        a.row_atom[R] = row_ok ? self : 0;
+        a.row_len[R] = row_ok ? len : 0;
     }
     if ((lane % SL) == 0) {
         a.slice_iters[slice] = iters;
@@ -278,16 +278,17 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
     }
 }
 
-// One block: longest row and total entries over all slices, and the overflow
-// flag of the context when a row did not fit.
+// One block per system: longest row and entries over the system's slices, in
+// a fixed order, and the overflow flag of the context when a row did not fit.
 __global__ __launch_bounds__(1024) void k_list_stats(const int32_t* __restrict__ slice_stats,
-                                                     int64_t nslices, int cap,
-                                                     lj_list_stats* stats, lj_dev_status* st) {
+                                                     const lj_sys* sys, lj_list_stats* stats,
+                                                     lj_dev_status* st) {
     __shared__ int smax[16];
     __shared__ unsigned long long ssum[16];
+    const lj_sys& sy = sys[blockIdx.x];
     int mx = 0;
     unsigned long long tot = 0;
-    for (int64_t k = threadIdx.x; k < nslices; k += 1024) {
+    for (int64_t k = sy.slice0 + threadIdx.x; k < sy.slice0 + sy.nslices; k += 1024) {
         mx = max(mx, slice_stats[2 * k]);
         tot += (unsigned long long)slice_stats[2 * k + 1];
     }
@@ -309,9 +310,9 @@ __global__ __launch_bounds__(1024) void k_list_stats(const int32_t* __restrict__
             mx = max(mx, smax[w]);
             tot += ssum[w];
         }
-        stats->max_row = mx;
-        stats->entries = tot;
-        if (mx > cap) atomicOr(&st->flags, LJ_DEV_ROW_OVERFLOW);
+        stats[blockIdx.x].max_row = mx;
+        stats[blockIdx.x].entries = tot;
+        if (mx > sy.cap) atomicOr(&st->flags, LJ_DEV_ROW_OVERFLOW);
     }
 }
 
@@ -340,32 +341,11 @@ lj_status launch_g(lj_ctx* ctx, const NeighArgs& a, bool half, bool anyfull) {
 
 }  // namespace
 
-lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l, double rs) {
+lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l) {
     NeighArgs a;
-    a.n = l->n;
     a.nslices = l->nslices;
-    // delta: a few roundings of the largest coordinate, so that the cell range
-    // of a point never misses a cell holding a pair with r < rs
-    double L = c->box[0] > c->box[1] ? c->box[0] : c->box[1];
-    L = L > c->box[2] ? L : c->box[2];
-    const double delta = 16.0 * 2.220446049250313e-16 * (L + rs);
-    const double rsd = rs + delta;
-    // FP32 culling: inflate by a relative 1e-5 (far above the FP32 rounding of
-    // the cell-relative quantities it is computed from)
-    a.rsd2f = (float)(rsd * rsd * (1.0 + 1e-5));
-    bool anyfull = false;
-    for (int d = 0; d < 3; ++d) {
-        a.nc[d] = c->nc[d];
-        a.box[d] = c->box[d];
-        a.half_box[d] = 0.5 * c->box[d];
-        a.inv_cs[d] = (double)c->nc[d] / c->box[d];
-        a.cs2f[d] = (float)(c->cs[d] * c->cs[d]);
-        a.reach[d] = (int)ceil(rsd / c->cs[d]);
-        a.full[d] = (c->nc[d] < 2 * a.reach[d] + 2) ? 1 : 0;
-        anyfull = anyfull || a.full[d];
-    }
-    a.rs2 = rs * rs;
-    a.cap = l->cap;
+    a.sys = l->dsys;
+    a.slice_sys = l->slice_sys;
     a.cell_start = c->cell_start;
     a.spos = c->spos;
     a.row_atom = l->row_atom;
@@ -373,14 +353,16 @@ lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l, double
     a.slice_iters = l->slice_iters;
     a.slice_stats = l->slice_stats;
     a.col = l->col;
+    bool anyfull = false;
+    for (const lj_sys& sy : l->hsys) anyfull = anyfull || sy.full[0] || sy.full[1] || sy.full[2];
     const bool half = l->kind == LJ_LIST_HALF;
     // lanes per row in the build: tuned value, at most the layout's
     int gb = ctx->tune[LJ_TUNE_BUILD_LANES];
     if (gb != 1 && gb != 2 && gb != 4) gb = 1;
     if (gb > l->lanes) gb = l->lanes;
     lj_status st;
-#define LJ_GB(G)                                                     \
-    (gb == 1 ? launch_g<G, 1>(ctx, a, half, anyfull)                 \
+#define LJ_GB(G)                                                              \
+    (gb == 1 ? launch_g<G, 1>(ctx, a, half, anyfull)                          \
              : gb == 2 ? launch_g<G, (G >= 2 ? 2 : 1)>(ctx, a, half, anyfull) \
                        : launch_g<G, (G >= 4 ? 4 : (G >= 2 ? 2 : 1))>(ctx, a, half, anyfull))
     switch (l->lanes) {
@@ -396,8 +378,8 @@ lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l, double
 #undef LJ_GB
     if (st) return st;
     lj_prof_scope prof(ctx, LJ_PROF_OTHER);
-    hipLaunchKernelGGL(k_list_stats, dim3(1), dim3(1024), 0, ctx->stream,
-                       (const int32_t*)l->slice_stats, l->nslices, l->cap, l->stats, ctx->st);
+    hipLaunchKernelGGL(k_list_stats, dim3((unsigned)l->nsys), dim3(1024), 0, ctx->stream,
+                       (const int32_t*)l->slice_stats, (const lj_sys*)l->dsys, l->stats, ctx->st);
     LJ_HIP(hipGetLastError());
     return LJ_OK;
 }

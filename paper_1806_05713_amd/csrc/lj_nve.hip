@@ -1,15 +1,18 @@
-// lj_nve.hip -- velocity-Verlet NVE integration around the force path.
+// lj_nve.hip -- velocity-Verlet NVE integration around the force path, for a
+// batch of independent systems (a single system is a batch of one).
 //
 // Per step (unit mass):
 //   k_drift : v += F dt/2; dx = v dt; x += dx, wrapped into [0, L);
 //             disp += dx, or disp = 0 at a rebuild step
 //   [rebuild: cells + list in place]
-//   forces  : F, potential energy, virial, pair count (lj_launch_forces)
+//   forces  : F, per-system potential energy, virial, pair count
 //   k_kick  : v += F dt/2; per-block partial sums of v^2/2 and max |disp|^2
-//   k_log   : one block sums the partials in a fixed order and writes the
-//             step's log row (PE, KE, W, max displacement, pairs)
-// Every product and sum is rounded on its own, as in the oracle's integrator.
-// Streaming kernels: about 100 bytes per atom per step, HBM bound.
+//   k_log   : one block per system sums its partials in a fixed order and
+//             writes the system's log row (PE, KE, W, max displacement, pairs)
+// The per-atom kernels run over the list's rows (256-row blocks, each inside
+// one system), so every block knows its system and box.  Every product and
+// sum is rounded on its own, as in the oracle's integrator.  These kernels
+// stream about 100 bytes per atom per step (HBM bound).
 #include <math.h>
 
 #include "lj_internal.h"
@@ -18,17 +21,17 @@ struct lj_nve {
     lj_ctx* ctx;
     lj_list* list;
     double *pos, *vel, *force, *log;
-    int64_t n, log_rows;
-    int layout, precision, rebuild_every;
-    double dt, box[3];
-    lj_force_params fp;
+    int64_t log_rows;
+    int layout, precision, rebuild_every, nsys;
+    double dt;
+    lj_fconst* fc;         // device, nsys
     double* disp;          // n x 3: displacement since the last build
-    double* partials;      // 2 per block: kinetic energy, max |disp|^2
-    double* scratch;       // potential energy, virial
-    int64_t* npairs;       // device
-    int64_t* dstep;        // device step counter (row of the next log entry - 1)
+    double* partials;      // 2 per row block: kinetic energy, max |disp|^2
+    double* pe_w;          // nsys potential energies, then nsys virials
+    int64_t* npairs;       // per system
+    int64_t* dstep;        // device step counter: log row of the current step
     int64_t steps;         // host step counter
-    int64_t blocks;
+    int64_t rblocks;       // 256-row blocks of the list
     hipGraph_t graph;
     hipGraphExec_t exec;
     hipStream_t cap_stream;
@@ -41,52 +44,68 @@ __device__ __forceinline__ double* comp(double* a, int64_t n, int64_t i, int d) 
     return LAYOUT == LJ_AOS4 ? a + 4 * i + d : a + (int64_t)d * n + i;
 }
 
+struct RowArgs {
+    double* pos;
+    double* vel;
+    const double* force;
+    double* disp;
+    int64_t n;             // atoms over all systems (SoA stride)
+    const lj_sys* sys;
+    const int32_t* slice_sys;
+    const int32_t* row_atom;
+    int C;                 // rows per slice
+    double* partials;
+    int64_t* dstep;
+};
+
 template <int LAYOUT>
-__global__ __launch_bounds__(LJ_BLOCK) void k_drift(double* __restrict__ pos,
-                                                    double* __restrict__ vel,
-                                                    const double* __restrict__ force,
-                                                    double* __restrict__ disp, int64_t n,
-                                                    double hdt, double dt, double Lx, double Ly,
-                                                    double Lz, int reset) {
+__global__ __launch_bounds__(LJ_BLOCK) void k_drift(RowArgs a, double hdt, double dt, int reset,
+                                                    int bump_step) {
 #pragma clang fp contract(off)
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double L[3] = {Lx, Ly, Lz};
+    const int64_t r = blockIdx.x * (int64_t)LJ_BLOCK + threadIdx.x;
+    const int sid = __builtin_amdgcn_readfirstlane(
+        a.slice_sys[(blockIdx.x * (int64_t)LJ_BLOCK) / a.C]);
+    const lj_sys& sy = a.sys[sid];
+    if (bump_step && blockIdx.x == 0 && threadIdx.x == 0) *a.dstep += 1;
+    if (r - sy.slice0 * a.C >= sy.n) return;
+    const int64_t i = a.row_atom[r];
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        double* pv = comp<LAYOUT>(vel, n, i, d);
-        double* px = comp<LAYOUT>(pos, n, i, d);
-        const double f = *comp<LAYOUT>(const_cast<double*>(force), n, i, d);
+        double* pv = comp<LAYOUT>(a.vel, a.n, i, d);
+        double* px = comp<LAYOUT>(a.pos, a.n, i, d);
+        const double f = *comp<LAYOUT>(const_cast<double*>(a.force), a.n, i, d);
+        const double L = sy.box[d];
         const double v = *pv + hdt * f;
         const double dx = dt * v;
         double x = *px + dx;
-        x = x - L[d] * floor(x / L[d]);
-        if (x >= L[d]) x = 0.0;
+        x = x - L * floor(x / L);
+        if (x >= L) x = 0.0;
         *pv = v;
         *px = x;
-        disp[3 * i + d] = reset ? 0.0 : disp[3 * i + d] + dx;
+        a.disp[3 * i + d] = reset ? 0.0 : a.disp[3 * i + d] + dx;
     }
 }
 
 template <int LAYOUT>
-__global__ __launch_bounds__(LJ_BLOCK) void k_kick(double* __restrict__ vel,
-                                                   const double* __restrict__ force,
-                                                   const double* __restrict__ disp, int64_t n,
-                                                   double hdt, double* __restrict__ partials) {
+__global__ __launch_bounds__(LJ_BLOCK) void k_kick(RowArgs a, double hdt) {
 #pragma clang fp contract(off)
     __shared__ double red[LJ_WAVES_PER_BLOCK][2];
-    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t r = blockIdx.x * (int64_t)LJ_BLOCK + threadIdx.x;
+    const int sid = __builtin_amdgcn_readfirstlane(
+        a.slice_sys[(blockIdx.x * (int64_t)LJ_BLOCK) / a.C]);
+    const lj_sys& sy = a.sys[sid];
     double ke = 0.0, d2 = 0.0;
-    if (i < n) {
+    if (r - sy.slice0 * a.C < sy.n) {
+        const int64_t i = a.row_atom[r];
         double v[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-            double* pv = comp<LAYOUT>(vel, n, i, d);
-            v[d] = *pv + hdt * *comp<LAYOUT>(const_cast<double*>(force), n, i, d);
+            double* pv = comp<LAYOUT>(a.vel, a.n, i, d);
+            v[d] = *pv + hdt * *comp<LAYOUT>(const_cast<double*>(a.force), a.n, i, d);
             *pv = v[d];
         }
         ke = 0.5 * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
-        const double* u = disp + 3 * i;
+        const double* u = a.disp + 3 * i;
         d2 = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
     }
 #pragma unroll
@@ -106,20 +125,23 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_kick(double* __restrict__ vel,
             k += red[w][0];
             m = fmax(m, red[w][1]);
         }
-        partials[2 * blockIdx.x] = k;
-        partials[2 * blockIdx.x + 1] = m;
+        a.partials[2 * blockIdx.x] = k;
+        a.partials[2 * blockIdx.x + 1] = m;
     }
 }
 
-// One block: fixed-order sums of the partials, then the log row of the step.
-// first != 0: step 0 (row 0, counter reset); else row = counter + 1.
+// One block per system: fixed-order sums of its row blocks' partials, then
+// the system's log row for the current step (row = *dstep).
 __global__ __launch_bounds__(1024) void k_log(const double* __restrict__ partials,
-                                              int64_t nblocks, const double* pe_w,
-                                              const int64_t* npairs, int64_t* dstep,
-                                              double* log, int64_t log_rows, int first) {
+                                              const lj_sys* sys, int C, const double* pe_w,
+                                              const int64_t* npairs, const int64_t* dstep,
+                                              double* log, int64_t log_rows, int nsys) {
     __shared__ double red[16][2];
+    const int s = blockIdx.x;
+    const lj_sys& sy = sys[s];
+    const int64_t b0 = sy.slice0 * C / LJ_BLOCK, b1 = (sy.slice0 + sy.nslices) * C / LJ_BLOCK;
     double ke = 0.0, d2 = 0.0;
-    for (int64_t b = threadIdx.x; b < nblocks; b += 1024) {
+    for (int64_t b = b0 + threadIdx.x; b < b1; b += 1024) {
         ke += partials[2 * b];
         d2 = fmax(d2, partials[2 * b + 1]);
     }
@@ -140,44 +162,69 @@ __global__ __launch_bounds__(1024) void k_log(const double* __restrict__ partial
             k += red[w][0];
             m = fmax(m, red[w][1]);
         }
-        const int64_t row = first ? 0 : *dstep + 1;
-        *dstep = row;
-        if (row < log_rows) {
-            double* r = log + 5 * row;
-            r[0] = pe_w[0];
-            r[1] = k;
-            r[2] = pe_w[1];
-            r[3] = sqrt(m);
-            r[4] = (double)*npairs;
+        const int64_t row = *dstep;
+        if (row >= 0 && row < log_rows) {
+            double* out = log + 5 * (row * nsys + s);
+            out[0] = pe_w[s];
+            out[1] = k;
+            out[2] = pe_w[nsys + s];
+            out[3] = sqrt(m);
+            out[4] = (double)npairs[s];
         }
     }
+}
+
+__global__ void k_set_step(int64_t* dstep, int64_t v) { *dstep = v; }
+
+RowArgs row_args(lj_nve* s) {
+    RowArgs a;
+    a.pos = s->pos;
+    a.vel = s->vel;
+    a.force = s->force;
+    a.disp = s->disp;
+    a.n = s->list->n;
+    a.sys = s->list->dsys;
+    a.slice_sys = s->list->slice_sys;
+    a.row_atom = s->list->row_atom;
+    a.C = LJ_WAVE / s->list->lanes;
+    a.partials = s->partials;
+    a.dstep = s->dstep;
+    return a;
+}
+
+lj_status forces(lj_nve* s) {
+    return lj_launch_forces(s->ctx, s->pos, s->layout, s->precision, s->list, s->fc, s->force,
+                            s->pe_w, s->pe_w + s->nsys, s->npairs);
+}
+
+lj_status log_row(lj_nve* s) {
+    hipLaunchKernelGGL(k_log, dim3((unsigned)s->nsys), dim3(1024), 0, s->ctx->stream,
+                       (const double*)s->partials, (const lj_sys*)s->list->dsys,
+                       LJ_WAVE / s->list->lanes, (const double*)s->pe_w,
+                       (const int64_t*)s->npairs, (const int64_t*)s->dstep, s->log, s->log_rows,
+                       s->nsys);
+    LJ_HIP(hipGetLastError());
+    return LJ_OK;
 }
 
 template <int LAYOUT>
 lj_status enqueue_step(lj_nve* s, bool rebuild) {
     lj_ctx* ctx = s->ctx;
-    const dim3 grid((unsigned)s->blocks), block(LJ_BLOCK);
-    hipLaunchKernelGGL(k_drift<LAYOUT>, grid, block, 0, ctx->stream, s->pos, s->vel,
-                       (const double*)s->force, s->disp, s->n, 0.5 * s->dt, s->dt, s->box[0],
-                       s->box[1], s->box[2], rebuild ? 1 : 0);
+    const dim3 grid((unsigned)s->rblocks), block(LJ_BLOCK);
+    const RowArgs a = row_args(s);
+    hipLaunchKernelGGL(k_drift<LAYOUT>, grid, block, 0, ctx->stream, a, 0.5 * s->dt, s->dt,
+                       rebuild ? 1 : 0, 1);
     LJ_HIP(hipGetLastError());
     lj_status st;
     if (rebuild) {
         lj_list* l = s->list;
         if ((st = lj_launch_cells(ctx, s->pos, s->layout, l->cells))) return st;
-        if ((st = lj_launch_neighbors(ctx, l->cells, l, l->rc + l->skin))) return st;
+        if ((st = lj_launch_neighbors(ctx, l->cells, l))) return st;
     }
-    if ((st = lj_launch_forces(ctx, s->pos, s->list, s->fp, s->force, s->scratch,
-                               s->scratch + 1, s->npairs)))
-        return st;
-    hipLaunchKernelGGL(k_kick<LAYOUT>, grid, block, 0, ctx->stream, s->vel,
-                       (const double*)s->force, (const double*)s->disp, s->n, 0.5 * s->dt,
-                       s->partials);
-    hipLaunchKernelGGL(k_log, dim3(1), dim3(1024), 0, ctx->stream, (const double*)s->partials,
-                       s->blocks, (const double*)s->scratch, (const int64_t*)s->npairs, s->dstep,
-                       s->log, s->log_rows, 0);
+    if ((st = forces(s))) return st;
+    hipLaunchKernelGGL(k_kick<LAYOUT>, grid, block, 0, ctx->stream, row_args(s), 0.5 * s->dt);
     LJ_HIP(hipGetLastError());
-    return LJ_OK;
+    return log_row(s);
 }
 
 lj_status step(lj_nve* s, bool rebuild) {
@@ -190,91 +237,31 @@ void release(lj_nve* s) {
     if (s->exec) (void)hipGraphExecDestroy(s->exec);
     if (s->graph) (void)hipGraphDestroy(s->graph);
     if (s->cap_stream) (void)hipStreamDestroy(s->cap_stream);
+    if (s->fc) (void)hipFree(s->fc);
     if (s->disp) (void)hipFree(s->disp);
     if (s->partials) (void)hipFree(s->partials);
-    if (s->scratch) (void)hipFree(s->scratch);
+    if (s->pe_w) (void)hipFree(s->pe_w);
     if (s->npairs) (void)hipFree(s->npairs);
     if (s->dstep) (void)hipFree(s->dstep);
     delete s;
 }
 
-}  // namespace
-
-lj_status lj_nve_make(lj_ctx* ctx, double* pos, double* vel, double* force, int64_t n,
-                      int32_t layout, const double box[3], double eps, double sigma, double rc,
-                      int32_t precision, lj_list* list, double dt, int32_t rebuild_every,
-                      double* log, int64_t log_rows, lj_nve** out) {
-    lj_nve* s = new (std::nothrow) lj_nve();
-    if (!s) return lj_fail(LJ_E_NOMEM, "host allocation");
-    s->ctx = ctx;
-    s->list = list;
-    s->pos = pos;
-    s->vel = vel;
-    s->force = force;
-    s->log = log;
-    s->n = n;
-    s->log_rows = log_rows;
-    s->layout = layout;
-    s->precision = precision;
-    s->rebuild_every = rebuild_every;
-    s->dt = dt;
-    for (int d = 0; d < 3; ++d) {
-        s->box[d] = box[d];
-        s->fp.box[d] = box[d];
-    }
-    s->fp.eps = eps;
-    s->fp.sigma = sigma;
-    s->fp.rc = rc;
-    s->fp.layout = layout;
-    s->fp.precision = precision;
-    s->blocks = (n + LJ_BLOCK - 1) / LJ_BLOCK;
-    hipError_t e = hipMalloc((void**)&s->disp, (size_t)n * 3 * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&s->partials, (size_t)s->blocks * 2 * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&s->scratch, 2 * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&s->npairs, sizeof(int64_t));
-    if (e == hipSuccess) e = hipMalloc((void**)&s->dstep, sizeof(int64_t));
-    if (e != hipSuccess) {
-        release(s);
-        return lj_hip_fail(e, "hipMalloc");
-    }
-    *out = s;
-    return LJ_OK;
-}
-
-lj_status lj_nve_start(lj_nve* s) {
-    lj_ctx* ctx = s->ctx;
-    lj_status st;
-    if ((st = lj_launch_zero(ctx->stream, s->disp, s->n * 3 * (int64_t)sizeof(double)))) return st;
-    if ((st = lj_launch_forces(ctx, s->pos, s->list, s->fp, s->force, s->scratch, s->scratch + 1,
-                               s->npairs)))
-        return st;
-    // kinetic energy of the initial velocities: a kick of zero length
-    const dim3 grid((unsigned)s->blocks), block(LJ_BLOCK);
-    if (s->layout == LJ_AOS4)
-        hipLaunchKernelGGL(k_kick<LJ_AOS4>, grid, block, 0, ctx->stream, s->vel,
-                           (const double*)s->force, (const double*)s->disp, s->n, 0.0,
-                           s->partials);
-    else
-        hipLaunchKernelGGL(k_kick<LJ_SOA>, grid, block, 0, ctx->stream, s->vel,
-                           (const double*)s->force, (const double*)s->disp, s->n, 0.0,
-                           s->partials);
-    hipLaunchKernelGGL(k_log, dim3(1), dim3(1024), 0, ctx->stream, (const double*)s->partials,
-                       s->blocks, (const double*)s->scratch, (const int64_t*)s->npairs, s->dstep,
-                       s->log, s->log_rows, 1);
-    LJ_HIP(hipGetLastError());
-    s->steps = 0;
-    return LJ_OK;
-}
-
-static lj_status capture_cycle(lj_nve* s) {
+lj_status capture_cycle(lj_nve* s) {
     lj_ctx* ctx = s->ctx;
     if (!s->cap_stream) LJ_HIP(hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking));
+    // the capture stream must see everything already queued on the context's stream
+    hipEvent_t ev;
+    LJ_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    hipError_t e = hipEventRecord(ev, ctx->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s->cap_stream, ev, 0);
+    (void)hipEventDestroy(ev);
+    if (e != hipSuccess) return lj_hip_fail(e, "capture stream ordering");
     hipStream_t saved = ctx->stream;
     const bool prof = ctx->prof_on;
     ctx->prof_on = false;
     ctx->stream = s->cap_stream;
     lj_status st = LJ_OK;
-    hipError_t e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed);
+    e = hipStreamBeginCapture(s->cap_stream, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) {
         st = lj_hip_fail(e, "hipStreamBeginCapture");
     } else {
@@ -293,6 +280,65 @@ static lj_status capture_cycle(lj_nve* s) {
     ctx->stream = saved;
     ctx->prof_on = prof;
     return st;
+}
+
+}  // namespace
+
+lj_status lj_nve_make(lj_ctx* ctx, double* pos, double* vel, double* force, int32_t layout,
+                      const lj_fconst* hfc, int32_t precision, lj_list* list, double dt,
+                      int32_t rebuild_every, double* log, int64_t log_rows, lj_nve** out) {
+    lj_nve* s = new (std::nothrow) lj_nve();
+    if (!s) return lj_fail(LJ_E_NOMEM, "host allocation");
+    s->ctx = ctx;
+    s->list = list;
+    s->pos = pos;
+    s->vel = vel;
+    s->force = force;
+    s->log = log;
+    s->log_rows = log_rows;
+    s->layout = layout;
+    s->precision = precision;
+    s->rebuild_every = rebuild_every;
+    s->nsys = list->nsys;
+    s->dt = dt;
+    s->rblocks = list->nslices * (LJ_WAVE / list->lanes) / LJ_BLOCK;
+    const int64_t n = list->n;
+    hipError_t e = hipMalloc((void**)&s->disp, (size_t)n * 3 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&s->fc, (size_t)s->nsys * sizeof(lj_fconst));
+    if (e == hipSuccess)
+        e = hipMalloc((void**)&s->partials, (size_t)s->rblocks * 2 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&s->pe_w, (size_t)s->nsys * 2 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc((void**)&s->npairs, (size_t)s->nsys * sizeof(int64_t));
+    if (e == hipSuccess) e = hipMalloc((void**)&s->dstep, sizeof(int64_t));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->fc, hfc, (size_t)s->nsys * sizeof(lj_fconst), hipMemcpyHostToDevice,
+                           ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        release(s);
+        return lj_hip_fail(e, "integrator allocation");
+    }
+    *out = s;
+    return LJ_OK;
+}
+
+lj_status lj_nve_start(lj_nve* s) {
+    lj_ctx* ctx = s->ctx;
+    lj_status st;
+    if ((st = lj_launch_zero(ctx->stream, s->disp, s->list->n * 3 * (int64_t)sizeof(double))))
+        return st;
+    hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, ctx->stream, s->dstep, (int64_t)0);
+    if ((st = forces(s))) return st;
+    // kinetic energy of the initial velocities: a kick of zero length
+    const dim3 grid((unsigned)s->rblocks), block(LJ_BLOCK);
+    if (s->layout == LJ_AOS4)
+        hipLaunchKernelGGL(k_kick<LJ_AOS4>, grid, block, 0, ctx->stream, row_args(s), 0.0);
+    else
+        hipLaunchKernelGGL(k_kick<LJ_SOA>, grid, block, 0, ctx->stream, row_args(s), 0.0);
+    LJ_HIP(hipGetLastError());
+    if ((st = log_row(s))) return st;
+    s->steps = 0;
+    return LJ_OK;
 }
 
 lj_status lj_nve_advance(lj_nve* s, int32_t nsteps, int32_t use_graph) {

@@ -34,7 +34,8 @@ EXPORTS = ["lj_create", "lj_destroy", "lj_set_stream", "lj_sync", "lj_build_cell
            "lj_cells_info", "lj_cells_export", "lj_cells_free", "lj_build_neighbors",
            "lj_update_neighbors", "lj_list_info", "lj_list_pairs", "lj_list_free",
            "lj_list_device_view", "lj_forces", "lj_nve_create", "lj_nve_init", "lj_nve_run",
-           "lj_nve_steps", "lj_nve_free",
+           "lj_nve_steps", "lj_nve_free", "lj_build_neighbors_batch", "lj_forces_batch",
+           "lj_list_sys_info", "lj_nve_create_batch",
            "lj_profile_begin", "lj_profile_end", "lj_tune_set", "lj_tune_get", "lj_last_error"]
 LJ_TUNE_BUILD_LANES, LJ_TUNE_FORCE_BATCH, LJ_TUNE_CELL_DIV, LJ_TUNE_N = 0, 1, 2, 3
 LJ_PROF_CELLS, LJ_PROF_NEIGH, LJ_PROF_FORCE, LJ_PROF_OTHER, LJ_PROF_N = 0, 1, 2, 3, 4
@@ -58,7 +59,7 @@ class ListDesc(ctypes.Structure):
                 ("cap", ctypes.c_int32), ("max_row", ctypes.c_int32),
                 ("entries", ctypes.c_int64), ("slots", ctypes.c_int64),
                 ("rc", ctypes.c_double), ("skin", ctypes.c_double),
-                ("box", ctypes.c_double * 3), ("nc", ctypes.c_int32 * 3)]
+                ("box", ctypes.c_double * 3), ("nc", ctypes.c_int32 * 3), ("nsys", ctypes.c_int32)]
 
 
 _lib = None
@@ -98,6 +99,12 @@ def load(path: str = LIB_PATH):
         "lj_forces": ([_VP, _VP, i64, i32, _D3, dbl, dbl, dbl, _VP, i32, _VP, _VP, _VP, _VP]),
         "lj_nve_create": ([_VP, _VP, _VP, _VP, i64, i32, _D3, dbl, dbl, dbl, i32, _VP, dbl, i32,
                            _VP, i64, PP]),
+        "lj_nve_create_batch": ([_VP, _VP, _VP, _VP, i32, _VP, _VP, _VP, i32, _VP, dbl, i32,
+                                 _VP, i64, PP]),
+        "lj_build_neighbors_batch": ([_VP, _VP, i32, i32, _VP, _VP, _VP, dbl, i32, i32, PP]),
+        "lj_forces_batch": ([_VP, _VP, i32, _VP, _VP, _VP, _VP, i32, _VP, _VP, _VP, _VP]),
+        "lj_list_sys_info": ([_VP, i32, ctypes.POINTER(i64), ctypes.POINTER(i32),
+                              ctypes.POINTER(i64), ctypes.POINTER(i32)]),
         "lj_nve_init": ([_VP]),
         "lj_nve_run": ([_VP, i32, i32]),
         "lj_nve_steps": ([_VP, ctypes.POINTER(i64)]),
@@ -242,6 +249,13 @@ class NeighborList:
         _check(load().lj_list_device_view(self.h, ctypes.byref(v)), "lj_list_device_view")
         return v
 
+    def sys_info(self, s: int):
+        """(n, max_row, entries, cap) of system s."""
+        n, mr, e, cap = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+        _check(load().lj_list_sys_info(self.h, int(s), ctypes.byref(n), ctypes.byref(mr),
+                                       ctypes.byref(e), ctypes.byref(cap)), "lj_list_sys_info")
+        return n.value, mr.value, e.value, cap.value
+
     def pairs(self) -> np.ndarray:
         """(entries, 2) int32 array of the stored (i, j) entries."""
         d = self.info()
@@ -310,26 +324,82 @@ def lj_forces(ctx: Context, pos, box, eps: float, sigma: float, rc: float,
     return force, out[0:1], out[1:2], cnt
 
 
+def _harr(a, dtype):
+    return np.ascontiguousarray(np.asarray(a, dtype=dtype))
+
+
+def _pos_layout_total(pos) -> Tuple[int, int]:
+    return _pos_layout(pos)
+
+
+def lj_build_neighbors_batch(ctx: Context, pos, n, box, rc, skin: float,
+                             kind: int = LJ_LIST_FULL, lanes: int = 0) -> NeighborList:
+    """Batch list: n[s] atoms per system, box (nsys, 3), rc (nsys,), concatenated pos."""
+    _, layout = _pos_layout(pos)
+    n = _harr(n, np.int64)
+    box = _harr(box, np.float64).reshape(-1, 3)
+    rc = _harr(rc, np.float64)
+    h = _VP()
+    _check(load().lj_build_neighbors_batch(ctx.h, _ptr(pos), layout, int(n.size), n.ctypes.data,
+                                           box.ctypes.data, rc.ctypes.data, float(skin),
+                                           int(kind), int(lanes), ctypes.byref(h)),
+           "lj_build_neighbors_batch")
+    nl = NeighborList(ctx, h)
+    nl._keep = (n, box, rc)
+    return nl
+
+
+def lj_forces_batch(ctx: Context, pos, nlist: NeighborList, eps, sigma, rc,
+                    precision: int = LJ_FP64, force=None):
+    """(force, energy[nsys], virial[nsys], npairs[nsys]) as device tensors."""
+    import torch
+    _, layout = _pos_layout(pos)
+    eps, sigma, rc = _harr(eps, np.float64), _harr(sigma, np.float64), _harr(rc, np.float64)
+    ns = int(eps.size)
+    if force is None:
+        force = torch.empty_like(pos)
+    e = torch.empty(ns, dtype=torch.float64, device=pos.device)
+    w = torch.empty(ns, dtype=torch.float64, device=pos.device)
+    c = torch.empty(ns, dtype=torch.int64, device=pos.device)
+    _check(load().lj_forces_batch(ctx.h, _ptr(pos), layout, nlist.h, eps.ctypes.data,
+                                  sigma.ctypes.data, rc.ctypes.data, int(precision), _ptr(force),
+                                  _ptr(e), _ptr(w), _ptr(c)), "lj_forces_batch")
+    return force, e, w, c
+
+
 class NVE:
     """Velocity-Verlet integrator bound to device arrays pos, vel, force (same
     layout) and a device log of log_rows x 5 doubles (lj_nve_create)."""
 
-    def __init__(self, ctx: Context, pos, vel, force, box, eps: float, sigma: float, rc: float,
+    def __init__(self, ctx: Context, pos, vel, force, box, eps, sigma, rc,
                  nlist: NeighborList, dt: float, rebuild_every: int = 10,
-                 precision: int = LJ_FP64, log_rows: int = 0):
+                 precision: int = LJ_FP64, log_rows: int = 0, batch: bool = False):
+        """Single system: box (3,), scalar eps, sigma, rc; log (log_rows, 5).
+        batch=True: per-system arrays eps, sigma, rc; log (log_rows, nsys, 5)."""
         import torch
         n, layout = _pos_layout(pos)
         for t in (vel, force):
             if t.shape != pos.shape or t.dtype != pos.dtype:
                 raise ValueError("vel and force must match pos in shape and dtype")
         self.ctx, self.pos, self.vel, self.force, self.nlist = ctx, pos, vel, force, nlist
-        self.log = torch.zeros((max(log_rows, 1), 5), dtype=torch.float64, device=pos.device)
         h = _VP()
-        _check(load().lj_nve_create(ctx.h, _ptr(pos), _ptr(vel), _ptr(force), n, layout,
-                                    _box(box), float(eps), float(sigma), float(rc),
-                                    int(precision), nlist.h, float(dt), int(rebuild_every),
-                                    _ptr(self.log), int(log_rows), ctypes.byref(h)),
-               "lj_nve_create")
+        if batch:
+            eps, sigma, rc = _harr(eps, np.float64), _harr(sigma, np.float64), _harr(rc, np.float64)
+            ns = int(eps.size)
+            self.log = torch.zeros((max(log_rows, 1), ns, 5), dtype=torch.float64,
+                                   device=pos.device)
+            _check(load().lj_nve_create_batch(ctx.h, _ptr(pos), _ptr(vel), _ptr(force), layout,
+                                              eps.ctypes.data, sigma.ctypes.data, rc.ctypes.data,
+                                              int(precision), nlist.h, float(dt),
+                                              int(rebuild_every), _ptr(self.log), int(log_rows),
+                                              ctypes.byref(h)), "lj_nve_create_batch")
+        else:
+            self.log = torch.zeros((max(log_rows, 1), 5), dtype=torch.float64, device=pos.device)
+            _check(load().lj_nve_create(ctx.h, _ptr(pos), _ptr(vel), _ptr(force), n, layout,
+                                        _box(box), float(eps), float(sigma), float(rc),
+                                        int(precision), nlist.h, float(dt), int(rebuild_every),
+                                        _ptr(self.log), int(log_rows), ctypes.byref(h)),
+                   "lj_nve_create")
         self.h = h
 
     def init(self):

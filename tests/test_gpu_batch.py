@@ -1,0 +1,162 @@
+"""Batched systems (one launch per phase for all systems): every system of
+the batch against the oracle run on that system alone."""
+import numpy as np
+import pytest
+
+from oracle.ljref import half_pairs_set
+from paper_1806_05713_amd import synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def lj():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1806_05713_amd import lj
+    return lj
+
+
+@pytest.fixture(scope="module")
+def ctx(lj):
+    c = lj.Context(0, stream=torch.cuda.Stream())
+    yield c
+    c.close()
+
+
+def small_batch(count=24, seed=7):
+    return synth.batch512(count=count, nmin=256, nmax=2048, seed=seed)
+
+
+def concat(systems, layout=0):
+    pos = np.concatenate([s.pos for s in systems])
+    return torch.from_numpy(synth.aos4(pos) if layout == 0 else synth.soa(pos)).to("cuda")
+
+
+def offsets(systems):
+    return np.concatenate([[0], np.cumsum([s.n for s in systems])])
+
+
+def params(systems):
+    n = np.array([s.n for s in systems])
+    box = np.array([s.box for s in systems])
+    rc = np.array([s.rc for s in systems])
+    return n, box, rc
+
+
+def canon(ij):
+    a = np.sort(ij.astype(np.int64), axis=1)
+    return a[np.lexsort((a[:, 1], a[:, 0]))]
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("layout", [0, 1])
+def test_batch_pairs_and_forces(lj, ctx, oracle, kind, layout):
+    systems = small_batch()
+    off = offsets(systems)
+    n, box, rc = params(systems)
+    pos = concat(systems, layout)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(ctx.stream):
+        nl = lj.lj_build_neighbors_batch(ctx, pos, n, box, rc, 0.3, kind=kind)
+        ones = np.ones(len(systems))
+        F, E, W, C = lj.lj_forces_batch(ctx, pos, nl, ones, ones, rc)
+        ctx.sync()
+    torch.cuda.synchronize()
+    ij = nl.pairs().astype(np.int64)
+    sys_of = np.searchsorted(off, ij[:, 0], side="right") - 1
+    assert np.all(sys_of == np.searchsorted(off, ij[:, 1], side="right") - 1)
+    f = F.cpu().numpy()
+    f = f[:, :3] if layout == 0 else f.T
+    E, W, C = E.cpu().numpy(), W.cpu().numpy(), C.cpu().numpy()
+    for s, sy in enumerate(systems):
+        rp, col = oracle.cell_pairs(sy.pos, sy.box, sy.rc + sy.skin)
+        ref = half_pairs_set(rp, col)
+        mine = ij[sys_of == s] - off[s]
+        if kind == 1:
+            mine = mine[mine[:, 0] < mine[:, 1]]
+        assert np.array_equal(canon(mine), ref), f"system {s}"
+        Fr, Er, Wr, nr = oracle.forces(sy.pos, sy.box, 1.0, 1.0, sy.rc, rp, col)
+        scale = max(np.abs(Fr).max(), 24.0)
+        assert np.abs(f[off[s]:off[s + 1]] - Fr).max() <= 1e-10 * scale, f"system {s}"
+        assert abs(E[s] - Er) <= 1e-12 * abs(Er)
+        assert abs(W[s] - Wr) <= 1e-12 * abs(Wr)
+        assert C[s] == nr
+        n_s, max_row, entries, cap = nl.sys_info(s)
+        assert n_s == sy.n and max_row <= cap
+        assert entries == (1 if kind == 0 else 2) * ref.shape[0]
+
+
+def run_batch_nve(lj, ctx, systems, dt, nsteps, every, use_graph, precision=0):
+    n, box, rc = params(systems)
+    pos = concat(systems)
+    vel = torch.from_numpy(synth.aos4(np.concatenate([s.vel for s in systems]))).to("cuda")
+    force = torch.zeros_like(pos)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(ctx.stream):
+        nl = lj.lj_build_neighbors_batch(ctx, pos, n, box, rc, 0.3, kind=1)
+        ones = np.ones(len(systems))
+        nve = lj.NVE(ctx, pos, vel, force, None, ones, ones, rc, nl, dt, every, precision,
+                     log_rows=nsteps + 1, batch=True)
+        nve.init()
+        nve.run(nsteps, use_graph=use_graph)
+        ctx.sync()
+    torch.cuda.synchronize()
+    out = pos.cpu().numpy()[:, :3].copy(), vel.cpu().numpy()[:, :3].copy(), nve.log.cpu().numpy().copy()
+    nve.free()
+    nl.free()
+    return out
+
+
+def test_batch_nve_matches_oracle(lj, ctx, oracle):
+    systems = small_batch(count=10, seed=11)
+    off = offsets(systems)
+    p, v, log = run_batch_nve(lj, ctx, systems, 0.005, 25, 10, use_graph=False)
+    for s, sy in enumerate(systems):
+        pr, vr, _, lr = oracle.nve(sy.pos, sy.vel, sy.box, 1.0, 1.0, sy.rc, sy.skin, 0.005, 25, 10)
+        d = p[off[s]:off[s + 1]] - pr
+        d -= sy.box[0] * np.round(d / sy.box[0])
+        assert np.abs(d).max() < 1e-9, f"system {s}"
+        assert np.abs(v[off[s]:off[s + 1]] - vr).max() < 1e-8
+        np.testing.assert_allclose(log[:, s, 0], lr[:, 0], rtol=1e-9)
+        np.testing.assert_allclose(log[:, s, 1], lr[:, 1], rtol=1e-9)
+        np.testing.assert_allclose(log[:, s, 2], lr[:, 2], rtol=1e-9)
+        assert np.array_equal(log[:, s, 4], lr[:, 4])
+
+
+def test_batch_nve_graph_equals_eager(lj, ctx):
+    systems = small_batch(count=16, seed=12)
+    a = run_batch_nve(lj, ctx, systems, 0.005, 30, 10, use_graph=False)
+    b = run_batch_nve(lj, ctx, systems, 0.005, 30, 10, use_graph=True)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+
+
+def test_batch512_full_size(lj, ctx, oracle):
+    """The 512-system batch (about 4.3M atoms): exact pairs and forces for a
+    sample of systems, zero net force in every system."""
+    systems = synth.batch512()
+    off = offsets(systems)
+    n, box, rc = params(systems)
+    pos = concat(systems)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(ctx.stream):
+        nl = lj.lj_build_neighbors_batch(ctx, pos, n, box, rc, 0.3, kind=1)
+        ones = np.ones(len(systems))
+        F, E, W, C = lj.lj_forces_batch(ctx, pos, nl, ones, ones, rc)
+        ctx.sync()
+    torch.cuda.synchronize()
+    f = F.cpu().numpy()[:, :3]
+    E = E.cpu().numpy()
+    for s in range(len(systems)):
+        net = np.abs(f[off[s]:off[s + 1]].sum(axis=0)).max()
+        assert net <= 1e-10 * max(np.abs(f[off[s]:off[s + 1]]).max(), 24.0) * np.sqrt(systems[s].n)
+    rng = np.random.Generator(np.random.PCG64(3))
+    for s in sorted(rng.choice(len(systems), size=6, replace=False)) + [int(np.argmax(n)), int(np.argmin(n))]:
+        sy = systems[s]
+        rp, col = oracle.cell_pairs(sy.pos, sy.box, sy.rc + sy.skin)
+        Fr, Er, Wr, nr = oracle.forces(sy.pos, sy.box, 1.0, 1.0, sy.rc, rp, col)
+        assert np.abs(f[off[s]:off[s + 1]] - Fr).max() <= 1e-10 * max(np.abs(Fr).max(), 24.0)
+        assert abs(E[s] - Er) <= 1e-12 * abs(Er)
+        assert nl.sys_info(s)[2] == 2 * col.size
