@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
 FP64_VECTOR_TFLOPS = 78.6  # MI355X FP64 vector peak
+COPY_BYTES = 256 << 20     # size of the calibration copy (read once, written once)
 
 
 def algorithmic_force_bytes(n: int, entries: int) -> int:
@@ -88,6 +89,15 @@ def main():
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the variant matrix")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run three plain 256 MiB device-to-device copies (a known-size "
+                         "kernel that scales HBM byte counters)")
+    ap.add_argument("--workload", choices=["lj131k", "lj4m", "batch512", "accuracy"],
+                    default="lj131k",
+                    help="lj131k (default): build + forces on the 131k-atom fluid; lj4m: "
+                         "100-step NVE of the 4M-atom fluid; batch512: 100-step NVE of 512 "
+                         "batched systems; accuracy: 10,000-step mixed vs FP64 run on the "
+                         "500k-atom fluid (use --steps to shorten)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
@@ -101,6 +111,22 @@ def main():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.workload != "lj131k":
+        from paper_1806_05713_amd import workloads
+        if args.workload == "accuracy":
+            result = workloads.accuracy_lj500k(steps=args.steps)
+        else:
+            fn = workloads.bench_lj4m if args.workload == "lj4m" else workloads.bench_batch512
+            result = fn(steps=args.steps, warmup=args.warmup, cpu=not args.no_cpu)
+        print(json.dumps(result), flush=True)
+        return
     ctx = lj.Context(0)
 
     s = synth.lj131k()

@@ -358,7 +358,7 @@ lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l) {
     const bool half = l->kind == LJ_LIST_HALF;
     // lanes per row in the build: tuned value, at most the layout's
     int gb = ctx->tune[LJ_TUNE_BUILD_LANES];
-    if (gb != 1 && gb != 2 && gb != 4) gb = 1;
+    if (gb != 1 && gb != 2 && gb != 4) gb = 4;
     if (gb > l->lanes) gb = l->lanes;
     lj_status st;
 #define LJ_GB(G)                                                              \

@@ -1,0 +1,275 @@
+"""Measured workloads beyond the default benchmark: the 4M-atom NVE run and
+the 512-system batched NVE run.  Each returns one result dictionary in the
+benchmark's JSON format (pair interactions per second of whole MD steps,
+with per-phase kernel times from HIP events on the library's stream).
+
+An MD step here is: drift, the in-place list rebuild every 10th step, forces,
+kick, and the per-step log; 100 steps captured as HIP-graph cycles of 10.
+"""
+from __future__ import annotations
+
+import sys
+import time
+
+import numpy as np
+
+from . import lj, synth
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _note(msg: str) -> None:
+    print(f"[workload] {msg}", file=sys.stderr, flush=True)
+
+
+def _nve_run(ctx, pos, vel, force, box, eps, sigma, rc, nl, dt, steps, precision, batch):
+    import torch
+    nve = lj.NVE(ctx, pos, vel, force, box, eps, sigma, rc, nl, dt, 10, precision,
+                 log_rows=steps + 1, batch=batch)
+    nve.init()
+    ctx.sync()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(ctx.stream)
+    nve.run(steps, use_graph=True)
+    ev1.record(ctx.stream)
+    ctx.sync()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    log = nve.log.cpu().numpy().copy()
+    nve.free()
+    return ms, log
+
+
+def _phase_profile(ctx, pos, vel, force, box, eps, sigma, rc, nl, dt, precision, batch, steps=20):
+    """Per-phase device time per step (us) from the library's profiler on eager steps."""
+    nve = lj.NVE(ctx, pos, vel, force, box, eps, sigma, rc, nl, dt, 10, precision,
+                 log_rows=0, batch=batch)
+    nve.init()
+    ctx.profile_begin()
+    nve.run(steps, use_graph=False)
+    prof = ctx.profile_end()
+    nve.free()
+    return {k: round(v[0] * 1e3 / steps, 3) for k, v in prof.items()}
+
+
+def _drift(log, dt, e_index=None):
+    """Total-energy drift per 1,000 steps: slope of a linear fit of
+    (E(t) - E(0)) / |E(0)| against the step number, times 1,000."""
+    et = log[..., 0] + log[..., 1]
+    if et.ndim == 2:
+        et = et.sum(axis=1)
+    x = np.arange(et.shape[0], dtype=np.float64)
+    y = (et - et[0]) / abs(et[0])
+    return float(np.polyfit(x, y, 1)[0] * 1000.0)
+
+
+def bench_lj4m(steps: int = 100, warmup: int = 0, cpu: bool = False):
+    import torch
+    dev = torch.device("cuda:0")
+    s = synth.lj4m()
+    ctx = lj.Context(0, stream=torch.cuda.Stream())
+    out = {}
+    for prec_name, prec in (("fp64", lj.LJ_FP64), ("mixed", lj.LJ_MIXED)):
+        with torch.cuda.stream(ctx.stream):
+            pos = torch.from_numpy(synth.aos4(s.pos)).to(dev)
+            vel = torch.from_numpy(synth.aos4(s.vel)).to(dev)
+            force = torch.zeros_like(pos)
+            torch.cuda.synchronize()
+            nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=lj.LJ_LIST_FULL)
+            ms, log = _nve_run(ctx, pos, vel, force, s.box, 1.0, 1.0, s.rc, nl, 0.005, steps,
+                               prec, False)
+            prof = _phase_profile(ctx, pos, vel, force, s.box, 1.0, 1.0, s.rc, nl, 0.005, prec,
+                                  False)
+            entries = nl.info().entries
+            nl.free()
+        _note(f"lj4m: {prec_name} done")
+        pairs = float(log[1:, 4].mean())
+        out[prec_name] = {"ms_per_step": round(ms / steps, 4),
+                          "pairs_per_s": round(pairs / (ms / steps * 1e-3), 1),
+                          "force_pairs_per_s": round(pairs / (prof["force"] * 1e-6), 1),
+                          "phase_us_per_step": prof,
+                          "energy_drift_per_1000_steps": _drift(log, 0.005),
+                          "list_entries": entries}
+    f64 = out["fp64"]
+    force_bytes = s.n * (32 + 32 + 8) + 4 * f64["list_entries"]
+    gbs = force_bytes / (f64["phase_us_per_step"]["force"] * 1e-6) / 1e9
+    return {
+        "metric": "pair interactions/s (FP64 vs FP32/FP64-mixed) at rho=1, rc=3; HBM GB/s",
+        "value": f64["pairs_per_s"], "unit": "pair interactions/s", "n_gpus": 1,
+        "steps": steps, "warmup": warmup, "ms_per_step": f64["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "FP64 LJ fluid, 4,000,000 atoms (100^3 FCC x4), rho=0.85, "
+                               "Maxwell T=1.0, rc=2.5, skin=0.3, 100 velocity-Verlet steps at "
+                               "dt=0.005, list rebuilt every 10 steps, HIP-graph cycles",
+                   "atoms": s.n, "list": "full", "layout": "aos4"},
+        "roofline": {"kernel": "k_force (FP64, full list)", "bound": "hbm",
+                     "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                     "bytes_per_launch": force_bytes,
+                     "us_per_launch": f64["phase_us_per_step"]["force"]},
+        "fp64": f64, "mixed": out["mixed"],
+        "mixed_speedup_force": round(f64["phase_us_per_step"]["force"] /
+                                     out["mixed"]["phase_us_per_step"]["force"], 3),
+    }
+
+
+def bench_batch512(steps: int = 100, warmup: int = 0, cpu: bool = False):
+    import torch
+    dev = torch.device("cuda:0")
+    systems = synth.batch512()
+    n = np.array([x.n for x in systems])
+    box = np.array([x.box for x in systems])
+    rc = np.array([x.rc for x in systems])
+    ones = np.ones(len(systems))
+    pos0 = np.concatenate([x.pos for x in systems])
+    vel0 = np.concatenate([x.vel for x in systems])
+    ctx = lj.Context(0, stream=torch.cuda.Stream())
+    out = {}
+    for prec_name, prec in (("fp64", lj.LJ_FP64), ("mixed", lj.LJ_MIXED)):
+        with torch.cuda.stream(ctx.stream):
+            pos = torch.from_numpy(synth.aos4(pos0)).to(dev)
+            vel = torch.from_numpy(synth.aos4(vel0)).to(dev)
+            force = torch.zeros_like(pos)
+            torch.cuda.synchronize()
+            nl = lj.lj_build_neighbors_batch(ctx, pos, n, box, rc, 0.3, kind=lj.LJ_LIST_FULL)
+            ms, log = _nve_run(ctx, pos, vel, force, None, ones, ones, rc, nl, 0.005, steps,
+                               prec, True)
+            prof = _phase_profile(ctx, pos, vel, force, None, ones, ones, rc, nl, 0.005, prec,
+                                  True)
+            nl.free()
+        _note(f"batch512: {prec_name} done")
+        pairs = float(log[1:, :, 4].sum(axis=1).mean())
+        out[prec_name] = {"ms_per_step": round(ms / steps, 4),
+                          "pairs_per_s": round(pairs / (ms / steps * 1e-3), 1),
+                          "phase_us_per_step": prof,
+                          "energy_drift_per_1000_steps_total": _drift(log, 0.005)}
+    # batching gain: one batched force launch vs one launch per system
+    with torch.cuda.stream(ctx.stream):
+        pos = torch.from_numpy(synth.aos4(pos0)).to(dev)
+        torch.cuda.synchronize()
+        nl = lj.lj_build_neighbors_batch(ctx, pos, n, box, rc, 0.3, kind=lj.LJ_LIST_FULL)
+        F = torch.empty_like(pos)
+        lj.lj_forces_batch(ctx, pos, nl, ones, ones, rc, force=F)
+        ctx.sync()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            lj.lj_forces_batch(ctx, pos, nl, ones, ones, rc, force=F)
+        ctx.sync()
+        t_batched = (time.perf_counter() - t0) / 10
+        nl.free()
+        off = np.concatenate([[0], np.cumsum(n)])
+        singles = []
+        for k, x in enumerate(systems):
+            p = pos[off[k]:off[k + 1]].contiguous()
+            singles.append((p, lj.lj_build_neighbors(ctx, p, x.box, x.rc, 0.3,
+                                                     kind=lj.LJ_LIST_FULL), x))
+        outs = [(torch.empty_like(p), torch.empty(2, dtype=torch.float64, device=dev))
+                for p, _, _ in singles]
+        ctx.sync()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            for (p, l1, x), (f1, o1) in zip(singles, outs):
+                lj.lj_forces(ctx, p, x.box, 1.0, 1.0, x.rc, l1, lj.LJ_FP64, f1, o1)
+        ctx.sync()
+        t_loop = (time.perf_counter() - t0) / 3
+        for _, l1, _ in singles:
+            l1.free()
+    f64 = out["fp64"]
+    return {
+        "metric": "pair interactions/s (FP64 vs FP32/FP64-mixed) at rho=1, rc=3; HBM GB/s",
+        "value": f64["pairs_per_s"], "unit": "pair interactions/s", "n_gpus": 1,
+        "steps": steps, "warmup": warmup, "ms_per_step": f64["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "512 independent LJ systems, N ~ U{256..16384} (total "
+                               f"{int(n.sum())} atoms), rho ~ U[0.7, 1.1], rc ~ U[2.5, 3.0], "
+                               "skin 0.3, jittered FCC, T=1.0; one launch per phase for all "
+                               "systems, 100-step NVE as HIP-graph cycles of 10",
+                   "systems": len(systems), "atoms": int(n.sum())},
+        "fp64": f64, "mixed": out["mixed"],
+        "force_batched_ms": round(t_batched * 1e3, 3),
+        "force_per_system_launch_loop_ms": round(t_loop * 1e3, 3),
+        "batching_gain_force": round(t_loop / t_batched, 2),
+    }
+
+
+def accuracy_lj500k(steps: int = 10000, rebuild_every: int = 10):
+    """Mixed-precision accuracy run on the 500,000-atom fluid (rho = 1.0,
+    T = 0.7, rc = 3.0, skin = 0.3, dt = 0.005), FP64 and mixed trajectories
+    from the same initial state.
+
+    Per step of the mixed trajectory, the FP64 kernel re-evaluates the forces
+    on the same positions with the same list; the error is
+    max_i |F_mixed_i - F_fp64_i| / max_i |F_fp64_i| (norms per component).
+    Step 0 is the perfect lattice, where every force vanishes by symmetry and
+    both kernels return rounding residues, so the relative statistics cover
+    steps 1..N and step 0 is reported as absolute values.  Energy drift per
+    1,000 steps is the slope of a linear fit of (E_tot(t) - E_tot(0)) /
+    |E_tot(0)| for each trajectory."""
+    import torch
+    dev = torch.device("cuda:0")
+    s = synth.lj500k()
+    ctx = lj.Context(0, stream=torch.cuda.Stream())
+    res = {}
+    with torch.cuda.stream(ctx.stream):
+        for prec_name, prec in (("fp64", lj.LJ_FP64), ("mixed", lj.LJ_MIXED)):
+            pos = torch.from_numpy(synth.aos4(s.pos)).to(dev)
+            vel = torch.from_numpy(synth.aos4(s.vel)).to(dev)
+            force = torch.zeros_like(pos)
+            nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=lj.LJ_LIST_FULL)
+            nve = lj.NVE(ctx, pos, vel, force, s.box, 1.0, 1.0, s.rc, nl, 0.005, rebuild_every,
+                         prec, log_rows=steps + 1)
+            nve.init()
+            t0 = time.perf_counter()
+            if prec == lj.LJ_FP64:
+                nve.run(steps, use_graph=True)
+                ctx.sync()
+            else:
+                f64 = torch.empty_like(pos)
+                out = torch.empty(2, dtype=torch.float64, device=dev)
+                err = torch.empty(steps + 1, dtype=torch.float64, device=dev)
+                fmax = torch.empty(steps + 1, dtype=torch.float64, device=dev)
+                e_f = torch.empty(steps + 1, dtype=torch.float64, device=dev)
+                for k in range(steps + 1):
+                    if k:
+                        nve.run(1, use_graph=False)
+                    if k % 1000 == 0:
+                        _note(f"accuracy: mixed step {k}")
+                    lj.lj_forces(ctx, pos, s.box, 1.0, 1.0, s.rc, nl, lj.LJ_FP64, f64, out)
+                    err[k] = (force[:, :3] - f64[:, :3]).abs().amax()
+                    fmax[k] = f64[:, :3].abs().amax()
+                    e_f[k] = out[0]
+                ctx.sync()
+            wall = time.perf_counter() - t0
+            log = nve.log.cpu().numpy().copy()
+            nve.free()
+            nl.free()
+            _note(f"accuracy: {prec_name} trajectory done in {wall:.1f} s")
+            r = {"wall_s": round(wall, 2),
+                 "energy_drift_per_1000_steps": _drift(log, 0.005),
+                 "E0": float(log[0, 0] + log[0, 1]),
+                 "E_end": float(log[-1, 0] + log[-1, 1]),
+                 "max_abs_rel_dE": float(np.max(np.abs((log[:, 0] + log[:, 1]) /
+                                                       (log[0, 0] + log[0, 1]) - 1.0))),
+                 "T_end": float(2.0 * log[-1, 1] / (3 * s.n - 3))}
+            if prec == lj.LJ_MIXED:
+                d = err.cpu().numpy()
+                fm = fmax.cpu().numpy()
+                e = d[1:] / fm[1:]
+                pe_mixed = log[:, 0]
+                pe_f64 = e_f.cpu().numpy()
+                r.update({"force_rel_err_max": float(e.max()),
+                          "force_rel_err_mean": float(e.mean()),
+                          "force_rel_err_p99": float(np.quantile(e, 0.99)),
+                          "force_rel_err_argmax_step": int(e.argmax()) + 1,
+                          "step0_abs_err": float(d[0]), "step0_max_abs_f64": float(fm[0]),
+                          "max_abs_f64_min_over_steps": float(fm[1:].min()),
+                          "pe_rel_err_max": float(np.max(np.abs(pe_mixed / pe_f64 - 1.0)))})
+            res[prec_name] = r
+    return {"workload": "mixed-precision accuracy run: 500,000 atoms (50^3 FCC x4), rho=1.0, "
+                        "Maxwell T=0.7, rc=3.0, skin=0.3, dt=0.005, list rebuilt every "
+                        f"{rebuild_every} steps, {steps} velocity-Verlet steps, full list",
+            "atoms": s.n, "steps": steps, **res}
