@@ -40,6 +40,35 @@ def algorithmic_force_bytes(n: int, entries: int) -> int:
     return n * (32 + 32 + 8) + 4 * entries
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_lj131k_hbm_traffic.txt")
+
+
+def measured_traffic(path: str = TRAFFIC_FILE):
+    """HBM bytes per force launch from the committed counter summary (two
+    rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE, scaled by a plain copy),
+    or None when the summary is missing or the force-kernel sources have
+    changed since the counters were taken."""
+    import hashlib
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    try:
+        h = hashlib.sha256()
+        for src in kv["source_files"].split():
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != kv["source_sha256"]:
+            return None
+        return int(kv["traffic_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
+
+
 def time_steps(torch, fn, steps: int, warmup: int):
     for _ in range(warmup):
         fn()
@@ -168,7 +197,9 @@ def main():
     roofline = {"kernel": "k_force (FP64, full list)" if kind == lj.LJ_LIST_FULL
                 else "k_force (FP64, half list)",
                 "bound": "hbm", "achieved": round(force_gbs, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(force_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(force_gbs / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic() if (kind == lj.LJ_LIST_FULL and args.lanes in (0, 8))
+                else None,
                 "bytes_per_launch": bytes_force, "us_per_launch": round(force_us, 3)}
     dominant = "force" if force_us >= neigh_us else "neigh"
 

@@ -58,10 +58,14 @@ extern "C" {
 #define LJ_API
 #endif
 
+/* Largest atom count of one call (all systems of a batch together): kernels
+ * address 32-byte records with 32-bit byte offsets. */
+#define LJ_MAX_ATOMS (1LL << 27)
+
 typedef enum {
     LJ_OK = 0,
-    LJ_E_INVALID = -1,   /* NULL pointer, n < 1, rc <= 0, skin < 0, eps/sigma <= 0,
-                            non-finite parameter, unknown enum value */
+    LJ_E_INVALID = -1,   /* NULL pointer, n < 1, n > LJ_MAX_ATOMS, rc <= 0, skin < 0,
+                            eps/sigma <= 0, non-finite parameter, unknown enum value */
     LJ_E_BOX = -2,       /* some box[d] < 2 (rc + skin) */
     LJ_E_POSITION = -3,  /* a coordinate is non-finite or outside [0, box[d]) */
     LJ_E_CAPACITY = -4,  /* a fixed capacity was exceeded (see the call) */

@@ -110,7 +110,8 @@ lj_status check_common(lj_ctx* ctx, const double* pos, int64_t n, int32_t layout
     if (!ctx) return lj_fail(LJ_E_INVALID, "context is NULL");
     if (!pos) return lj_fail(LJ_E_INVALID, "positions are NULL");
     if (n < 1) return lj_fail(LJ_E_INVALID, "n must be >= 1");
-    if (n > (int64_t)INT32_MAX / 2) return lj_fail(LJ_E_INVALID, "n exceeds the 32-bit index range");
+    if (n > LJ_MAX_ATOMS)
+        return lj_fail(LJ_E_INVALID, "n exceeds LJ_MAX_ATOMS (2^27 atoms per call)");
     if (layout != LJ_AOS4 && layout != LJ_SOA) return lj_fail(LJ_E_INVALID, "unknown layout");
     if (layout == LJ_AOS4 && ((uintptr_t)pos & 31u))
         return lj_fail(LJ_E_INVALID, "LJ_AOS4 positions must be 32-byte aligned");

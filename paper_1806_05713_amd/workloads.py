@@ -258,7 +258,7 @@ def accuracy_lj500k(steps: int = 10000, rebuild_every: int = 10):
             if prec == lj.LJ_MIXED:
                 d = err.cpu().numpy()
                 fm = fmax.cpu().numpy()
-                e = d[1:] / fm[1:]
+                e = d[1:] / np.maximum(fm[1:], 24.0)   # floor 24 eps/sigma = |F(sigma)|
                 pe_mixed = log[:, 0]
                 pe_f64 = e_f.cpu().numpy()
                 r.update({"force_rel_err_max": float(e.max()),

@@ -4,10 +4,12 @@ Each test checks the oracle against mathematics or crystallography:
 closed forms of the 12-6 potential at special distances, F = -grad E by
 central differences, W = -dE/dlambda under uniform scaling, Newton's third
 law, the FCC shell structure, lattice sums by direct enumeration of lattice
-vectors, the O(N^2) definition of the list, invariances, and energy
+vectors, the O(N^2) definition of the list, the values the paper prints for
+its benchmark system (tests/golden), invariances, and energy
 conservation of velocity Verlet.  None of these runs on a GPU.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -231,17 +233,40 @@ def test_cell_list_equals_definition_131k(oracle):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+def _paper_values():
+    vals = {}
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_benchmark.txt")
+    with open(path) as f:
+        for line in f:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                k, v = (x.strip() for x in line.split("="))
+                vals[k] = float(v)
+    return vals
+
+
 def test_list_rows_match_paper_count(oracle):
-    # The paper quotes roughly 55 to 80 j atoms per i atom for its benchmark
-    # (FCC, rho = 1, rc = 3, Sec. V.D).  The half list at rs = 3.3 over a
-    # jittered lattice gives rows in that range on average.
-    s = synth.lj4k()
+    # The paper's benchmark system (Sec. II): 119,164 atoms at number density
+    # 1.0 with cutoff 3.0, i.e. 31^3 FCC unit cells.  Its rows hold about 55 to
+    # 80 j atoms per i atom (Sec. V.D).  The half list of that system at the
+    # search length rc + 0.3 must give rows in that range on average, and so
+    # must the pairs inside rc alone.
+    pv = _paper_values()
+    n_cells = round((pv["atoms"] / 4) ** (1 / 3))
+    assert 4 * n_cells ** 3 == pv["atoms"]
+    s = synth.small_fcc(n_cells, pv["density"], 0.05, 31, rc=pv["cutoff"])
+    assert s.n == pv["atoms"]
+    assert abs(s.n / np.prod(s.box) - pv["density"]) < 1e-12
     rp, col = oracle.cell_pairs(s.pos, s.box, s.rc + s.skin)
     rows = np.diff(rp)
-    assert 55 <= rows.mean() <= 80
+    assert pv["neighbors_min"] <= rows.mean() <= pv["neighbors_max"]
+    _, _, _, n_in = oracle.forces(s.pos, s.box, 1.0, 1.0, s.rc, rp, col)
+    assert pv["neighbors_min"] <= n_in / s.n <= pv["neighbors_max"]
     # every unordered pair once: row sums of a half list are half the full count
-    _, _, _, nrs, _ = oracle.sample(s.pos, s.box, 1, 1, s.rc, s.rc + s.skin, np.arange(s.n))
-    assert 2 * col.size == int(nrs.sum())
+    t = synth.lj4k()
+    rp4, col4 = oracle.cell_pairs(t.pos, t.box, t.rc + t.skin)
+    _, _, _, nrs, _ = oracle.sample(t.pos, t.box, 1, 1, t.rc, t.rc + t.skin, np.arange(t.n))
+    assert 2 * col4.size == int(nrs.sum())
 
 
 def test_permutation_equivariance(oracle):
