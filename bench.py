@@ -115,7 +115,9 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--kind", choices=["full", "half"], default="full")
-    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--lanes", type=int, default=0, help="lanes per list row (0: default)")
+    ap.add_argument("--build-lanes", type=int, default=0,
+                    help="lanes per row in the list build, 1, 2 or 4 (0: default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the variant matrix")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -157,6 +159,8 @@ def main():
         print(json.dumps(result), flush=True)
         return
     ctx = lj.Context(0)
+    if args.build_lanes:
+        ctx.tune_set(lj.LJ_TUNE_BUILD_LANES, args.build_lanes)
 
     s = synth.lj131k()
     kind = lj.LJ_LIST_FULL if args.kind == "full" else lj.LJ_LIST_HALF

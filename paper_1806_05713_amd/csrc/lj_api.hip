@@ -217,7 +217,7 @@ lj_status alloc_cells(int nsys, const int64_t* n, const double* box, const doubl
     if ((st = dmalloc(&c->dsys, nsys)) || (st = dmalloc(&c->count, cells)) ||
         (st = dmalloc(&c->cell_start, cells + 1)) || (st = dmalloc(&c->cid, atoms)) ||
         (st = dmalloc(&c->order_tmp, atoms)) || (st = dmalloc(&c->order, atoms)) ||
-        (st = dmalloc(&c->spos, atoms)) ||
+        (st = dmalloc(&c->spos, atoms + LJ_SPOS_PAD)) ||
         (st = dmalloc(&c->block_sums, lj_scan_workspace(cells)))) {
         cells_release(c);
         return st;
@@ -329,6 +329,7 @@ lj_status build_list(lj_ctx* ctx, const double* pos, int32_t layout, int nsys, c
     l->nsys = nsys;
     l->kind = kind;
     l->lanes = lanes;
+    l->build_lanes = lj_build_lanes(ctx, lanes);
     l->fc_valid = false;
     lj_status st;
     const lj_cells* c = cells;

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_cell_sort(
             double x, y, z;
             load_xyz(pos, n, layout, v, x, y, z);
             order[s0 + rank] = v;
-            spos[s0 + rank] = make_double4(x, y, z, (double)v);
+            spos[s0 + rank] = make_double4(x, y, z, __longlong_as_double((long long)v));
         }
     }
 }

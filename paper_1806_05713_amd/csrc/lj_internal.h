@@ -10,8 +10,9 @@
 //   cells      count[ncell], cell_start[ncell + 1] over the concatenated cell
 //              grids (system s owns cells [cell0, cell0 + ncell_s)), cid[N]
 //              (cell of atom), order[N] (cell-sorted rank -> atom), spos[N]
-//              (cell-sorted double4 (x, y, z, atom index as a double)).  The
-//              ranks of system s are [atom0, atom0 + n).
+//              (cell-sorted double4 (x, y, z, w) whose w holds the atom index
+//              as the bits of a 64-bit integer) plus LJ_SPOS_PAD unused
+//              records.  The ranks of system s are [atom0, atom0 + n).
 //   list       wavefront-sliced rows: a slice is C = 64 / G rows served by one
 //              wavefront with G lanes per row; rows are the atoms in cell
 //              order.  System s owns slices [slice0, slice0 + nslices), a
@@ -38,6 +39,10 @@
 #define LJ_BLOCK 256
 #define LJ_WAVES_PER_BLOCK (LJ_BLOCK / LJ_WAVE)
 #define LJ_NXCD 8
+// Records past the end of the cell-sorted positions, so that a list-build lane
+// may load a whole batch of candidates past the end of its range (the extra
+// records are never used).
+#define LJ_SPOS_PAD 8
 
 // One system of a batch (device and host copies).
 struct lj_sys {
@@ -118,7 +123,7 @@ struct lj_cells {
     int32_t* cid;                  // n
     int32_t* order_tmp;            // n (unsorted within cells)
     int32_t* order;                // n
-    double4* spos;                 // n
+    double4* spos;                 // n + LJ_SPOS_PAD
     int32_t* block_sums;           // scan workspace
     bool counts_dirty;             // count[] may be non-zero (a build was interrupted)
 };
@@ -128,6 +133,7 @@ struct lj_list {
     int64_t n;
     int kind;
     int lanes;                     // G
+    int build_lanes;               // GB: lanes per row in the build, fixed at creation
     int64_t nslices, ncol;
     std::vector<lj_sys> hsys;      // all fields valid
     lj_sys* dsys;                  // device copy
@@ -159,6 +165,8 @@ lj_status lj_launch_cells(lj_ctx* ctx, const double* pos, int layout, lj_cells* 
 int64_t lj_scan_workspace(int64_t m);
 // neighbor list (lj_neigh.hip): rebuild every system of l from cells c
 lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l);
+// lanes per row the list build of a new list uses (tuning knob, <= lanes)
+int lj_build_lanes(const lj_ctx* ctx, int lanes);
 // forces (lj_force.hip): per-system energy, virial, pair count
 int64_t lj_force_blocks(int64_t nslices);
 lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int precision,

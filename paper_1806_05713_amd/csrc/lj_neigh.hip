@@ -5,7 +5,12 @@
 // Work mapping.  Rows are the atoms in cell order.  A wavefront builds
 // 64 / GB consecutive rows with GB lanes per row (GB <= G, the lanes per row
 // of the list layout), and appends straight into the wavefront-sliced slots of
-// the layout: a single pass, no count-then-fill.
+// the layout: a single pass, no count-then-fill.  With one lane per row
+// (GB = 1) each lane walks its own candidate range with NB candidate records
+// in flight at once (the range may be overrun by up to NB - 1 records, which
+// the cell-sorted position array is padded for; those lanes are masked); with
+// GB > 1 the lanes of a row test consecutive candidates and append in order
+// with a ballot.
 //
 // Candidate cells.  Cells have side >= rs/2 by default, so a neighbor lies
 // within R = 2 cells per dimension.  Each row visits only the (y, z) cell rows
@@ -24,6 +29,8 @@
 // the compare-and-subtract form does, because a pair reached through another
 // image has |t| >= L/2 >= rs and is rejected either way.  A dimension with
 // fewer cells is scanned whole with the compare form.
+#include <type_traits>
+
 #include "lj_internal.h"
 
 namespace {
@@ -58,11 +65,33 @@ __device__ __forceinline__ float cell_gap(int o, float f) {
     return o > 0 ? (float)o - f : (o < 0 ? f - (float)(o + 1) : 0.0f);
 }
 
+// Value of lane q of each group of GB consecutive lanes, for every lane of the
+// group (GB <= 4: one quad permutation of the data-parallel primitives).
+template <int GB, int Q>
+__device__ __forceinline__ int group_bcast(int v) {
+    if constexpr (GB == 1) {
+        return v;
+    } else if constexpr (GB == 2) {
+        return __builtin_amdgcn_mov_dpp(v, Q | (Q << 2) | ((2 + Q) << 4) | ((2 + Q) << 6), 0xF,
+                                        0xF, true);
+    } else {
+        return __builtin_amdgcn_mov_dpp(v, Q * 0x55, 0xF, 0xF, true);
+    }
+}
+template <int GB, int Q>
+__device__ __forceinline__ double group_bcast(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = group_bcast<GB, Q>((int)(b & 0xffffffffll)),
+              hi = group_bcast<GB, Q>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <int G, int GB, bool HALF, bool ANYFULL>
 __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
     constexpr int CB = LJ_WAVE / GB;   // rows per wavefront in the build
     constexpr int C = LJ_WAVE / G;     // rows per slice of the layout
     constexpr int SL = C * GB;         // lanes of the wavefront that hold one slice
+    constexpr int NB = LJ_SPOS_PAD;    // candidates in flight per lane when GB = 1
     const int lane = threadIdx.x & (LJ_WAVE - 1);
     const int wv = __builtin_amdgcn_readfirstlane(
         (int)lj_xcd_block(blockIdx.x, gridDim.x) * LJ_WAVES_PER_BLOCK + (threadIdx.x >> 6));
@@ -82,12 +111,17 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
     const int S = sy.cap / G;
     const int cap = sy.cap;
     const double rs2 = sy.rs2;
-    const int64_t slot0 = sy.col0 + (slice - sy.slice0) * (int64_t)S * LJ_WAVE + c * G;
-    int32_t* __restrict__ col = a.col;
+    // the wavefront's slots start at its first slice; a lane's row at lane_slot
+    const int64_t slice_first = row0 / C;
+    int32_t* __restrict__ wcol =
+        a.col + sy.col0 + (slice_first - sy.slice0) * (int64_t)S * LJ_WAVE;
+    const uint32_t lane_slot =
+        (uint32_t)((slice - slice_first) * (int64_t)S * LJ_WAVE) + (uint32_t)(c * G);
     const int32_t* __restrict__ cell_start = a.cell_start + sy.cell0;
+    const char* __restrict__ spos_b = reinterpret_cast<const char*>(a.spos);
 
     const double4 qi = a.spos[rank];
-    const int32_t self = (int32_t)qi.w;
+    const int32_t self = (int32_t)__double_as_longlong(qi.w);
     const int nx = sy.nc[0], ny = sy.nc[1], nz = sy.nc[2];
     // cell of the atom and its fractional position in the cell (FP32, culling only)
     const int cx = lj_cell_coord(qi.x, sy.inv_cs[0], nx);
@@ -102,16 +136,16 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
     const int Rx = sy.reach[0], Ry = fully ? 0 : sy.reach[1], Rz = fullz ? 0 : sy.reach[2];
     const int ky_n = fully ? ny : 2 * Ry + 1, kz_n = fullz ? nz : 2 * Rz + 1;
     const float rsd2f = sy.rsd2f;
+    const float inv_cs2x = 1.0f / sy.cs2f[0];
 
     // the ballot bits of this row's GB lanes
     const uint64_t grp = (GB == LJ_WAVE) ? ~0ull : (((1ull << (GB & 63)) - 1ull) << (cb * GB));
     const uint32_t grp_lo = (uint32_t)grp, grp_hi = (uint32_t)(grp >> 32);
     int cnt = 0;
 
-    // test candidates s0 .. s0+m-1 (cell-sorted ranks); x shifted by shx if shifted_x
-    auto test = [&](int s, double shx, double shy, double shz, bool shifted_x, int32_t& jv) {
-        const double4 qj = *reinterpret_cast<const double4*>(
-            reinterpret_cast<const char*>(a.spos) + (uint32_t)s * 32u);
+    // pair test of candidate rank s with record qj; x shifted by shx if shifted_x
+    auto test_q = [&](const double4& qj, int s, double shx, double shy, double shz,
+                      bool shifted_x, int32_t& jv) {
         double tx = qj.x - qi.x, ty = qj.y - qi.y, tz = qj.z - qi.z;
         if (ANYFULL) {
             tx = fullx ? nearest(tx, sy.box[0], sy.half_box[0]) : (shifted_x ? tx + shx : tx);
@@ -125,58 +159,72 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
         const double r2 = r2_rounded(tx, ty, tz);
         bool own = true;
         if (HALF) own = ((s > r32) != (((s + r32) & 1) != 0));
-        jv = (int32_t)qj.w;
-        // bitwise: no short-circuit branch around the loads
-        return (s != r32) & own & (r2 < rs2);
+        jv = (int32_t)__double_as_longlong(qj.w);
+        // bitwise: no short-circuit branch around the loads; the candidate is
+        // the row's own atom iff its index is
+        return (jv != self) & own & (r2 < rs2);
     };
+    auto test = [&](int s, double shx, double shy, double shz, bool shifted_x, int32_t& jv) {
+        const double4 qj = *reinterpret_cast<const double4*>(spos_b + (uint32_t)s * 32u);
+        return test_q(qj, s, shx, shy, shz, shifted_x, jv);
+    };
+    // entry k of the row: one store through the wavefront's base with a
+    // 32-bit offset
     auto put = [&](uint32_t k, int32_t jv) {
-        col[slot0 + (int64_t)(k / (uint32_t)G) * LJ_WAVE + (k % (uint32_t)G)] = jv;
+        wcol[lane_slot + (k / (uint32_t)G) * (uint32_t)LJ_WAVE + (k % (uint32_t)G)] = jv;
     };
     auto scan = [&](int s0, int m, double shx, double shy, double shz, bool shifted_x) {
         if (GB == 1) {
-            // one lane per row: each lane appends to its own row, no ballot
-            int f = 0;
-            for (; f + 1 < m; f += 2) {
-                int32_t j0, j1;
-                const bool p0 = test(s0 + f, shx, shy, shz, shifted_x, j0);
-                const bool p1 = test(s0 + f + 1, shx, shy, shz, shifted_x, j1);
-                if (p0) {
-                    if (cnt < cap) put((uint32_t)cnt, j0);
-                    ++cnt;
-                }
-                if (p1) {
-                    if (cnt < cap) put((uint32_t)cnt, j1);
-                    ++cnt;
-                }
-            }
-            if (f < m) {
-                int32_t j0;
-                if (test(s0 + f, shx, shy, shz, shifted_x, j0)) {
-                    if (cnt < cap) put((uint32_t)cnt, j0);
-                    ++cnt;
+            // one lane per row: each lane appends to its own row, no ballot;
+            // NB records in flight, loaded before any is tested
+            for (int f = 0; f < m; f += NB) {
+                const char* p = spos_b + (uint32_t)(s0 + f) * 32u;
+                double4 q[NB];
+#pragma unroll
+                for (int u = 0; u < NB; ++u) q[u] = *reinterpret_cast<const double4*>(p + 32 * u);
+#pragma unroll
+                for (int u = 0; u < NB; ++u) {
+                    int32_t jv;
+                    const bool pass =
+                        (f + u < m) & test_q(q[u], s0 + f + u, shx, shy, shz, shifted_x, jv);
+                    if (pass) {
+                        if (cnt < cap) put((uint32_t)cnt, jv);
+                        ++cnt;
+                    }
                 }
             }
         } else {
+            // the row's GB lanes test consecutive candidates; a lane past the
+            // end re-tests the last one (masked), so the test never branches
+            const int last = m > 0 ? m - 1 : 0;
             for (int base = 0; __any(base < m); base += GB) {
                 const int f = base + g;
-                bool pass = false;
-                int32_t jv = 0;
-                if (f < m) pass = test(s0 + f, shx, shy, shz, shifted_x, jv);
-                const uint64_t ball = __ballot(pass);
+                int32_t jv;
+                const bool pass =
+                    (f < m) & test(s0 + min(f, last), shx, shy, shz, shifted_x, jv);
+                const uint64_t ball = __builtin_amdgcn_ballot_w64(pass);
                 const uint32_t blo = (uint32_t)ball & grp_lo,
                                bhi = (uint32_t)(ball >> 32) & grp_hi;
                 const int k = cnt + (int)__builtin_amdgcn_mbcnt_hi(
                                         bhi, __builtin_amdgcn_mbcnt_lo(blo, 0u));
-                if (pass && k < cap) put((uint32_t)k, jv);
+                if (pass & (k < cap)) put((uint32_t)k, jv);
                 cnt += __builtin_popcount(blo) + __builtin_popcount(bhi);
             }
         }
     };
 
-    for (int kz = 0; kz < kz_n; ++kz) {
-        int wz;
-        double shz = 0.0;
-        float gz = 0.0f;
+    // Candidate ranges of (y, z) cell-row combination cc: segment A (cell
+    // rank range [a0, a1), x not shifted) and segment B ([b0, b1), x shifted
+    // by shb), with the y and z image shifts.
+    struct Seg {
+        int a0, a1, b0, b1;
+        double shy, shz, shb;
+    };
+    auto segment = [&](int cc) {
+        Seg sg = {0, 0, 0, 0, 0.0, 0.0, 0.0};
+        const int kz = cc / ky_n, ky = cc - kz * ky_n;
+        int wz, wy;
+        float gz = 0.0f, gy = 0.0f;
         if (fullz) {
             wz = kz;
         } else {
@@ -185,73 +233,91 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
             wz = cz + oz;
             if (wz < 0) {
                 wz += nz;
-                shz = -sy.box[2];
+                sg.shz = -sy.box[2];
             } else if (wz >= nz) {
                 wz -= nz;
-                shz = sy.box[2];
+                sg.shz = sy.box[2];
             }
         }
-        for (int ky = 0; ky < ky_n; ++ky) {
-            int wy;
-            double shy = 0.0;
-            float gy = 0.0f;
-            if (fully) {
-                wy = ky;
+        if (fully) {
+            wy = ky;
+        } else {
+            const int oy = ky - Ry;
+            gy = cell_gap(oy, fy);
+            wy = cy + oy;
+            if (wy < 0) {
+                wy += ny;
+                sg.shy = -sy.box[1];
+            } else if (wy >= ny) {
+                wy -= ny;
+                sg.shy = sy.box[1];
+            }
+        }
+        // squared distance from the atom to this cell row (FP32, conservative)
+        const float d2 = fmaf(gy * gy, sy.cs2f[1], gz * gz * sy.cs2f[2]);
+        int xa0 = 0, xa1 = 0, xb0 = 0, xb1 = 0;
+        if (row_ok && cc < ky_n * kz_n && d2 < rsd2f) {
+            if (fullx) {
+                xa1 = nx;
             } else {
-                const int oy = ky - Ry;
-                gy = cell_gap(oy, fy);
-                wy = cy + oy;
-                if (wy < 0) {
-                    wy += ny;
-                    shy = -sy.box[1];
-                } else if (wy >= ny) {
-                    wy -= ny;
-                    shy = sy.box[1];
-                }
-            }
-            // squared distance from the atom to this cell row (FP32, conservative)
-            const float d2 = fmaf(gy * gy, sy.cs2f[1], gz * gz * sy.cs2f[2]);
-            int xa0 = 0, xa1 = 0, xb0 = 0, xb1 = 0;
-            double shb = 0.0;
-            if (row_ok && d2 < rsd2f) {
-                if (fullx) {
+                // chord half-width in cells, inflated (far above the rounding
+                // of the FP32 quantities it comes from)
+                const float wcell =
+                    __builtin_amdgcn_sqrtf((rsd2f - d2) * inv_cs2x) * 1.00001f + 1e-5f;
+                int u0 = cx + (int)floorf(fx - wcell);
+                int u1 = cx + (int)floorf(fx + wcell);
+                u0 = max(u0, cx - Rx);
+                u1 = min(u1, cx + Rx);
+                if (u0 < 0) {           // [u0, -1] wraps to the top with -L
+                    xb0 = u0 + nx;
+                    xb1 = nx;
+                    sg.shb = -sy.box[0];
+                    xa1 = u1 + 1;
+                } else if (u1 >= nx) {  // [nx, u1] wraps to the bottom with +L
+                    xa0 = u0;
                     xa1 = nx;
+                    xb1 = u1 - nx + 1;
+                    sg.shb = sy.box[0];
                 } else {
-                    // chord half-width in cells, inflated
-                    const float wcell =
-                        __builtin_amdgcn_sqrtf((rsd2f - d2) / sy.cs2f[0]) * 1.00001f + 1e-5f;
-                    int u0 = cx + (int)floorf(fx - wcell);
-                    int u1 = cx + (int)floorf(fx + wcell);
-                    u0 = max(u0, cx - Rx);
-                    u1 = min(u1, cx + Rx);
-                    if (u0 < 0) {           // [u0, -1] wraps to the top with -L
-                        xb0 = u0 + nx;
-                        xb1 = nx;
-                        shb = -sy.box[0];
-                        xa1 = u1 + 1;
-                    } else if (u1 >= nx) {  // [nx, u1] wraps to the bottom with +L
-                        xa0 = u0;
-                        xa1 = nx;
-                        xb1 = u1 - nx + 1;
-                        shb = sy.box[0];
-                    } else {
-                        xa0 = u0;
-                        xa1 = u1 + 1;
-                    }
+                    xa0 = u0;
+                    xa1 = u1 + 1;
                 }
             }
-            const int rowbase = (wz * ny + wy) * nx;
-            int a0 = 0, a1 = 0, b0 = 0, b1 = 0;
-            if (xa1 > xa0) {
-                a0 = cell_start[rowbase + xa0];
-                a1 = cell_start[rowbase + xa1];
-            }
-            if (xb1 > xb0) {
-                b0 = cell_start[rowbase + xb0];
-                b1 = cell_start[rowbase + xb1];
-            }
-            scan(a0, a1 - a0, 0.0, shy, shz, false);
-            scan(b0, b1 - b0, shb, shy, shz, true);
+        }
+        const int rowbase = (wz * ny + wy) * nx;
+        if (xa1 > xa0) {
+            sg.a0 = cell_start[rowbase + xa0];
+            sg.a1 = cell_start[rowbase + xa1];
+        }
+        if (xb1 > xb0) {
+            sg.b0 = cell_start[rowbase + xb0];
+            sg.b1 = cell_start[rowbase + xb1];
+        }
+        return sg;
+    };
+    // the row's member q computed combination c0 + q for the whole row
+    auto scan_member = [&](const Seg& mine, auto qc) {
+        constexpr int Q = decltype(qc)::value;
+        const int a0 = group_bcast<GB, Q>(mine.a0), a1 = group_bcast<GB, Q>(mine.a1);
+        const int b0 = group_bcast<GB, Q>(mine.b0), b1 = group_bcast<GB, Q>(mine.b1);
+        const double shy = group_bcast<GB, Q>(mine.shy), shz = group_bcast<GB, Q>(mine.shz);
+        const double shb = group_bcast<GB, Q>(mine.shb);
+        scan(a0, a1 - a0, 0.0, shy, shz, false);
+        scan(b0, b1 - b0, shb, shy, shz, true);
+    };
+
+    // The (y, z) cell-row combinations, GB at a time: lane g of a row works
+    // out combination c0 + g, then the row scans the GB combinations in order.
+    const int ncombo = ky_n * kz_n;
+    for (int c0 = 0; c0 < ncombo; c0 += GB) {
+        const Seg mine = segment(c0 + g);
+        scan_member(mine, std::integral_constant<int, 0>());
+        if constexpr (GB > 1) {
+            if (c0 + 1 < ncombo) scan_member(mine, std::integral_constant<int, 1>());
+        }
+        if constexpr (GB > 2) {
+            if (c0 + 2 < ncombo) scan_member(mine, std::integral_constant<int, 2>());
+            if (c0 + 3 < ncombo) scan_member(mine, std::integral_constant<int, 3>());
         }
     }
 
@@ -341,6 +407,13 @@ lj_status launch_g(lj_ctx* ctx, const NeighArgs& a, bool half, bool anyfull) {
 
 }  // namespace
 
+int lj_build_lanes(const lj_ctx* ctx, int lanes) {
+    // tuned value (default 4), at most the layout's lanes per row
+    int gb = ctx->tune[LJ_TUNE_BUILD_LANES];
+    if (gb != 1 && gb != 2 && gb != 4) gb = 4;
+    return gb > lanes ? lanes : gb;
+}
+
 lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l) {
     NeighArgs a;
     a.nslices = l->nslices;
@@ -356,10 +429,7 @@ lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l) {
     bool anyfull = false;
     for (const lj_sys& sy : l->hsys) anyfull = anyfull || sy.full[0] || sy.full[1] || sy.full[2];
     const bool half = l->kind == LJ_LIST_HALF;
-    // lanes per row in the build: tuned value, at most the layout's
-    int gb = ctx->tune[LJ_TUNE_BUILD_LANES];
-    if (gb != 1 && gb != 2 && gb != 4) gb = 4;
-    if (gb > l->lanes) gb = l->lanes;
+    const int gb = l->build_lanes;
     lj_status st;
 #define LJ_GB(G)                                                              \
     (gb == 1 ? launch_g<G, 1>(ctx, a, half, anyfull)                          \
