@@ -145,6 +145,7 @@ void cells_release(lj_cells* c) {
     dfree(c->count);
     dfree(c->cell_start);
     dfree(c->cid);
+    dfree(c->slot);
     dfree(c->order_tmp);
     dfree(c->order);
     dfree(c->spos);
@@ -215,7 +216,7 @@ lj_status alloc_cells(int nsys, const int64_t* n, const double* box, const doubl
     }
     lj_status st;
     if ((st = dmalloc(&c->dsys, nsys)) || (st = dmalloc(&c->count, cells)) ||
-        (st = dmalloc(&c->cell_start, cells + 1)) || (st = dmalloc(&c->cid, atoms)) ||
+        (st = dmalloc(&c->cell_start, cells + 1)) || (st = dmalloc(&c->cid, atoms)) || (st = dmalloc(&c->slot, atoms)) ||
         (st = dmalloc(&c->order_tmp, atoms)) || (st = dmalloc(&c->order, atoms)) ||
         (st = dmalloc(&c->spos, atoms + LJ_SPOS_PAD)) ||
         (st = dmalloc(&c->block_sums, lj_scan_workspace(cells)))) {

@@ -1,15 +1,17 @@
 // lj_cells.hip -- cell binning and counting sort (the linked-list cell method
 // of Sec. III.B in array form, grouped with the counting sort of Sec. III.C).
 //
-//   k_bin        validate each position, compute its cell, count atoms per cell
-//   scan         exclusive prefix sum of the counts -> cell_start
-//   k_scatter    place each atom in its cell's range (order within a cell is
-//                whatever the atomics give)
-//   k_cell_sort  one wavefront per cell ranks the cell's atoms by index, so
-//                the final order is the stable counting-sort order, and writes
-//                the cell-sorted double4 copy (x, y, z, atom index)
-// All kernels are streaming passes over n atoms or ncell cells (HBM bound,
-// a few MB per call at 131k atoms).
+//   k_bin        validate each position, compute its cell, and take a slot of
+//                the cell with an atomic increment of its count
+//   scan         exclusive prefix sum of the counts -> cell_start; the counts
+//                are cleared as they are read, ready for the next build
+//   k_place      atom i goes to cell_start[cell] + slot (order within a cell
+//                is whatever the atomics gave)
+//   k_rank       one thread per atom ranks it among its cell's atoms by index,
+//                so the final order is the stable counting-sort order, and
+//                writes the cell-sorted double4 copy (x, y, z, atom index)
+// All kernels are streaming passes over n atoms or ncell cells (a few MB per
+// call at 131k atoms).
 #include "lj_internal.h"
 
 namespace {
@@ -41,6 +43,7 @@ struct BinArgs {
     const lj_sys* sys;
     const int32_t* atom_sys;   // system of each atom, or NULL for a single system
     int32_t* cid;
+    int32_t* slot;
     int32_t* count;
     lj_dev_status* st;
 };
@@ -63,47 +66,39 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_bin(BinArgs a) {
         atomicOr(&a.st->flags, LJ_DEV_BAD_POSITION);
     }
     a.cid[i] = (int32_t)c;
-    atomicAdd(&a.count[c], 1);
+    a.slot[i] = atomicAdd(&a.count[c], 1);
 }
 
-// Each atom takes a slot of its cell by counting the cell down from the top.
-__global__ __launch_bounds__(LJ_BLOCK) void k_scatter(int64_t n, const int32_t* __restrict__ cid,
-                                                      const int32_t* __restrict__ cell_start,
-                                                      int32_t* __restrict__ count,
-                                                      int32_t* __restrict__ order_tmp) {
+// Each atom goes to its slot of its cell's range.
+__global__ __launch_bounds__(LJ_BLOCK) void k_place(int64_t n, const int32_t* __restrict__ cid,
+                                                    const int32_t* __restrict__ slot,
+                                                    const int32_t* __restrict__ cell_start,
+                                                    int32_t* __restrict__ order_tmp) {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int c = cid[i];
-    const int k = atomicSub(&count[c], 1) - 1;
-    order_tmp[cell_start[c] + k] = (int32_t)i;
+    order_tmp[cell_start[cid[i]] + slot[i]] = (int32_t)i;
 }
 
-// One wavefront per cell: the rank of an atom within its cell is the number
-// of the cell's atoms with a smaller index.  Writes order[] and spos[].
-__global__ __launch_bounds__(LJ_BLOCK) void k_cell_sort(
-    int64_t ncell, int64_t n, const int32_t* __restrict__ cell_start,
-    const int32_t* __restrict__ order_tmp, const double* __restrict__ pos, int layout,
-    int32_t* __restrict__ order, double4* __restrict__ spos) {
-    const int lane = threadIdx.x & (LJ_WAVE - 1);
-    const int64_t cell = blockIdx.x * (int64_t)LJ_WAVES_PER_BLOCK + (threadIdx.x >> 6);
-    if (cell >= ncell) return;
-    const int s0 = cell_start[cell], s1 = cell_start[cell + 1];
-    const int m = s1 - s0;
-    for (int a = lane; a - lane < m; a += LJ_WAVE) {
-        const int v = a < m ? order_tmp[s0 + a] : INT32_MAX;
-        int rank = 0;
-        if (m <= LJ_WAVE) {
-            for (int b = 0; b < m; ++b) rank += (__shfl(v, b, LJ_WAVE) < v) ? 1 : 0;
-        } else {
-            for (int b = 0; b < m; ++b) rank += (order_tmp[s0 + b] < v) ? 1 : 0;
-        }
-        if (a < m) {
-            double x, y, z;
-            load_xyz(pos, n, layout, v, x, y, z);
-            order[s0 + rank] = v;
-            spos[s0 + rank] = make_double4(x, y, z, __longlong_as_double((long long)v));
-        }
-    }
+// One thread per position p of the cell-grouped order: the atom there is
+// ranked among its cell's atoms by index (the number with a smaller index),
+// which puts every cell in index order.  Writes order[] and spos[].
+__global__ __launch_bounds__(LJ_BLOCK) void k_rank(int64_t n, const int32_t* __restrict__ cid,
+                                                   const int32_t* __restrict__ cell_start,
+                                                   const int32_t* __restrict__ order_tmp,
+                                                   const double* __restrict__ pos, int layout,
+                                                   int32_t* __restrict__ order,
+                                                   double4* __restrict__ spos) {
+    const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int v = order_tmp[p];
+    const int c = cid[v];
+    const int s0 = cell_start[c], s1 = cell_start[c + 1];
+    int rank = 0;
+    for (int q = s0; q < s1; ++q) rank += (order_tmp[q] < v) ? 1 : 0;
+    double x, y, z;
+    load_xyz(pos, n, layout, v, x, y, z);
+    order[s0 + rank] = v;
+    spos[s0 + rank] = make_double4(x, y, z, __longlong_as_double((long long)v));
 }
 
 // ------------------------------------------------------------------ scan
@@ -133,9 +128,10 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* lds, int& total)
     return off + x - v;
 }
 
-__global__ __launch_bounds__(LJ_BLOCK) void k_scan_tile(const int32_t* __restrict__ in,
+__global__ __launch_bounds__(LJ_BLOCK) void k_scan_tile(int32_t* __restrict__ in,
                                                         int32_t* __restrict__ out, int64_t m,
-                                                        int32_t* __restrict__ tile_sums) {
+                                                        int32_t* __restrict__ tile_sums,
+                                                        int clear_in) {
     __shared__ int lds[LJ_WAVES_PER_BLOCK];
     const int64_t base = blockIdx.x * (int64_t)SCAN_TILE + threadIdx.x * (int64_t)SCAN_ITEMS;
     int v[SCAN_ITEMS];
@@ -144,6 +140,11 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_scan_tile(const int32_t* __restric
     for (int k = 0; k < SCAN_ITEMS; ++k) {
         v[k] = (base + k < m) ? in[base + k] : 0;
         s += v[k];
+    }
+    if (clear_in) {
+#pragma unroll
+        for (int k = 0; k < SCAN_ITEMS; ++k)
+            if (base + k < m) in[base + k] = 0;
     }
     int total;
     int run = block_exclusive_scan(s, lds, total);
@@ -177,24 +178,48 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_scan_sums(int32_t* __restrict__ su
     if (threadIdx.x == 0) *out_total = total;
 }
 
-// Small arrays: one block stages the whole array in LDS with coalesced loads,
-// each thread scans a contiguous chunk there, and the result is written back
-// coalesced.
+// Small arrays: one block.  The array is loaded with coalesced loads (all of
+// a thread's loads in flight at once) into LDS, padded by one word per 32 so
+// that thread t can then scan its contiguous chunk [32 t, 32 t + 32) without
+// bank conflicts; a block scan of the chunk totals gives each chunk its
+// offset, and the result goes back out coalesced.
 constexpr int SCAN1_THREADS = 1024;
-constexpr int64_t SCAN1_MAX = 32768;   // 128 KB of LDS
-__global__ __launch_bounds__(SCAN1_THREADS) void k_scan_single(const int32_t* __restrict__ in,
+constexpr int SCAN1_PER = 32;
+constexpr int64_t SCAN1_MAX = (int64_t)SCAN1_THREADS * SCAN1_PER;
+__device__ __forceinline__ int scan1_pad(int i) { return i + (i >> 5); }
+__global__ __launch_bounds__(SCAN1_THREADS) void k_scan_single(int32_t* __restrict__ in,
                                                                int32_t* __restrict__ out,
-                                                               int64_t m) {
-    __shared__ int buf[SCAN1_MAX];
+                                                               int64_t m, int clear_in) {
+    __shared__ int buf[SCAN1_MAX + SCAN1_MAX / 32];
     __shared__ int lds[SCAN1_THREADS / 64];
-    for (int64_t k = threadIdx.x; k < m; k += SCAN1_THREADS) buf[k] = in[k];
+    const int t = threadIdx.x;
+    {
+        int v[SCAN1_PER];
+#pragma unroll
+        for (int k = 0; k < SCAN1_PER; ++k) {
+            const int idx = k * SCAN1_THREADS + t;
+            v[k] = idx < m ? in[idx] : 0;
+        }
+#pragma unroll
+        for (int k = 0; k < SCAN1_PER; ++k) buf[scan1_pad(k * SCAN1_THREADS + t)] = v[k];
+        if (clear_in) {
+#pragma unroll
+            for (int k = 0; k < SCAN1_PER; ++k) {
+                const int idx = k * SCAN1_THREADS + t;
+                if (idx < m) in[idx] = 0;
+            }
+        }
+    }
     __syncthreads();
-    const int per = (int)((m + SCAN1_THREADS - 1) / SCAN1_THREADS);
-    const int b0 = threadIdx.x * per;
+    const int c0 = scan1_pad(t * SCAN1_PER);   // the chunk is contiguous in LDS
+    int v[SCAN1_PER];
     int s = 0;
-    for (int k = 0; k < per; ++k)
-        if (b0 + k < m) s += buf[b0 + k];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < SCAN1_PER; ++k) {
+        v[k] = buf[c0 + k];
+        s += v[k];
+    }
+    const int lane = t & 63, wave = t >> 6;
     int x = s;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
@@ -209,15 +234,18 @@ __global__ __launch_bounds__(SCAN1_THREADS) void k_scan_single(const int32_t* __
         tot += lds[w];
     }
     int run = off + x - s;
-    for (int k = 0; k < per; ++k)
-        if (b0 + k < m) {
-            const int v = buf[b0 + k];
-            buf[b0 + k] = run;
-            run += v;
-        }
+#pragma unroll
+    for (int k = 0; k < SCAN1_PER; ++k) {
+        buf[c0 + k] = run;
+        run += v[k];
+    }
     __syncthreads();
-    for (int64_t k = threadIdx.x; k < m; k += SCAN1_THREADS) out[k] = buf[k];
-    if (threadIdx.x == 0) out[m] = tot;
+#pragma unroll
+    for (int k = 0; k < SCAN1_PER; ++k) {
+        const int idx = k * SCAN1_THREADS + t;
+        if (idx < m) out[idx] = buf[scan1_pad(idx)];
+    }
+    if (t == 0) out[m] = tot;
 }
 
 __global__ __launch_bounds__(LJ_BLOCK) void k_scan_add(int32_t* __restrict__ out, int64_t m,
@@ -246,17 +274,19 @@ lj_status lj_launch_zero(hipStream_t s, void* p, int64_t bytes) {
     return LJ_OK;
 }
 
-lj_status lj_launch_scan(hipStream_t s, const int32_t* in, int32_t* out, int64_t m,
-                         int32_t* work) {
+lj_status lj_launch_scan(hipStream_t s, int32_t* in, int32_t* out, int64_t m, int32_t* work,
+                         bool clear_in) {
     const int64_t nt = (m + SCAN_TILE - 1) / SCAN_TILE;
     if (nt > SCAN_TILE) return lj_fail(LJ_E_CAPACITY, "scan: more than 16.7M elements");
     if (m == 0) return lj_launch_zero(s, out, sizeof(int32_t));
     if (m <= SCAN1_MAX) {
-        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SCAN1_THREADS), 0, s, in, out, m);
+        hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SCAN1_THREADS), 0, s, in, out, m,
+                           clear_in ? 1 : 0);
         LJ_HIP(hipGetLastError());
         return LJ_OK;
     }
-    hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)nt), dim3(LJ_BLOCK), 0, s, in, out, m, work);
+    hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)nt), dim3(LJ_BLOCK), 0, s, in, out, m, work,
+                       clear_in ? 1 : 0);
     hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(LJ_BLOCK), 0, s, work, nt, out + m);
     hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nt), dim3(LJ_BLOCK), 0, s, out, m,
                        (const int32_t*)work);
@@ -268,8 +298,8 @@ lj_status lj_launch_cells(lj_ctx* ctx, const double* pos, int layout, lj_cells* 
     hipStream_t s = ctx->stream;
     lj_prof_scope prof(ctx, LJ_PROF_CELLS);
     lj_status st;
-    // The per-cell counts are zero between builds: the scatter counts each
-    // cell back down to zero.  Clear them only after an interrupted build.
+    // The per-cell counts are zero between builds: the scan clears them as it
+    // reads them.  Clear them here only after an interrupted build.
     if (c->counts_dirty) {
         if ((st = lj_launch_zero(s, c->count, c->ncell * (int64_t)sizeof(int32_t)))) return st;
     }
@@ -281,19 +311,20 @@ lj_status lj_launch_cells(lj_ctx* ctx, const double* pos, int layout, lj_cells* 
     a.sys = c->dsys;
     a.atom_sys = c->atom_sys;
     a.cid = c->cid;
+    a.slot = c->slot;
     a.count = c->count;
     a.st = ctx->st;
     hipLaunchKernelGGL(k_bin, dim3(grid_for(c->n, LJ_BLOCK)), dim3(LJ_BLOCK), 0, s, a);
     LJ_HIP(hipGetLastError());
-    st = lj_launch_scan(s, c->count, c->cell_start, c->ncell, c->block_sums);
+    st = lj_launch_scan(s, c->count, c->cell_start, c->ncell, c->block_sums, true);
     if (st) return st;
-    hipLaunchKernelGGL(k_scatter, dim3(grid_for(c->n, LJ_BLOCK)), dim3(LJ_BLOCK), 0, s, c->n,
-                       (const int32_t*)c->cid, (const int32_t*)c->cell_start, c->count,
-                       c->order_tmp);
-    LJ_HIP(hipGetLastError());
     c->counts_dirty = false;
-    hipLaunchKernelGGL(k_cell_sort, dim3(grid_for(c->ncell, LJ_WAVES_PER_BLOCK)), dim3(LJ_BLOCK),
-                       0, s, c->ncell, c->n, (const int32_t*)c->cell_start,
+    hipLaunchKernelGGL(k_place, dim3(grid_for(c->n, LJ_BLOCK)), dim3(LJ_BLOCK), 0, s, c->n,
+                       (const int32_t*)c->cid, (const int32_t*)c->slot,
+                       (const int32_t*)c->cell_start, c->order_tmp);
+    LJ_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_rank, dim3(grid_for(c->n, LJ_BLOCK)), dim3(LJ_BLOCK), 0, s, c->n,
+                       (const int32_t*)c->cid, (const int32_t*)c->cell_start,
                        (const int32_t*)c->order_tmp, pos, layout, c->order, c->spos);
     LJ_HIP(hipGetLastError());
     return LJ_OK;

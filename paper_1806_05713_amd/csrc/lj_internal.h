@@ -121,6 +121,7 @@ struct lj_cells {
     int32_t* count;                // ncell
     int32_t* cell_start;           // ncell + 1
     int32_t* cid;                  // n
+    int32_t* slot;                 // n: slot of each atom in its cell (arbitrary order)
     int32_t* order_tmp;            // n (unsorted within cells)
     int32_t* order;                // n
     double4* spos;                 // n + LJ_SPOS_PAD
@@ -181,9 +182,10 @@ lj_status lj_nve_advance(lj_nve* s, int32_t nsteps, int32_t use_graph);
 void lj_nve_release(lj_nve* s);
 int64_t lj_nve_step_count(const lj_nve* s);
 lj_status lj_list_ensure_cells(lj_ctx* ctx, lj_list* l);
-// exclusive scan of m int32 values into out[0..m] (out[m] = total)
-lj_status lj_launch_scan(hipStream_t s, const int32_t* in, int32_t* out, int64_t m,
-                         int32_t* work);
+// exclusive scan of m int32 values into out[0..m] (out[m] = total); with
+// clear_in the input is zeroed as it is read
+lj_status lj_launch_scan(hipStream_t s, int32_t* in, int32_t* out, int64_t m, int32_t* work,
+                         bool clear_in);
 lj_status lj_launch_zero(hipStream_t s, void* p, int64_t bytes);
 // host: force constants of one system
 lj_fconst lj_make_fconst(double eps, double sigma, double rc);
