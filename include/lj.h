@@ -295,7 +295,8 @@ LJ_API lj_status lj_nve_free(lj_nve* nve);
 #define LJ_TUNE_FORCE_BATCH 1   /* list entries each lane has in flight in the force
                                    kernel: 2, 4 or 8; default 4 */
 #define LJ_TUNE_CELL_DIV 2      /* lists built without caller cells use cells of side
-                                   (rc + skin) / k, k = 1, 2, 3 or 4; default 2 */
+                                   (rc + skin) / k in y and z and half that in x,
+                                   k = 1, 2, 3 or 4; default 2 */
 #define LJ_TUNE_N 3
 /* Set knob `knob` to `value` (LJ_E_INVALID for an unknown knob or value). */
 LJ_API lj_status lj_tune_set(lj_ctx* ctx, int32_t knob, int32_t value);

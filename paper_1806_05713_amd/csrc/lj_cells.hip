@@ -102,10 +102,29 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_rank(int64_t n, const int32_t* __r
 }
 
 // ------------------------------------------------------------------ scan
-// Three-phase exclusive scan: per-block scan of SCAN_ITEMS x LJ_BLOCK values
-// with block totals, scan of the totals (one block), add back.
+// Large arrays, two passes over tiles of SCAN_ITEMS x LJ_BLOCK values: the
+// sum of every tile, then each tile adds up the sums of the tiles before it
+// and scans itself.
 constexpr int SCAN_ITEMS = 16;
 constexpr int SCAN_TILE = SCAN_ITEMS * LJ_BLOCK;   // 4096
+
+__device__ __forceinline__ int wave_isum(int x) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
+    return x;
+}
+
+// Sum over the block (every thread gets it).
+__device__ __forceinline__ int block_sum(int v, int* lds) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    v = wave_isum(v);
+    if (lane == 0) lds[wave] = v;
+    __syncthreads();
+    int t = 0;
+    for (int w = 0; w < LJ_WAVES_PER_BLOCK; ++w) t += lds[w];
+    __syncthreads();
+    return t;
+}
 
 __device__ __forceinline__ int block_exclusive_scan(int v, int* lds, int& total) {
     // wave inclusive scan
@@ -128,11 +147,30 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* lds, int& total)
     return off + x - v;
 }
 
-__global__ __launch_bounds__(LJ_BLOCK) void k_scan_tile(int32_t* __restrict__ in,
-                                                        int32_t* __restrict__ out, int64_t m,
-                                                        int32_t* __restrict__ tile_sums,
-                                                        int clear_in) {
+__global__ __launch_bounds__(LJ_BLOCK) void k_scan_reduce(const int32_t* __restrict__ in,
+                                                          int64_t m,
+                                                          int32_t* __restrict__ tile_sums) {
     __shared__ int lds[LJ_WAVES_PER_BLOCK];
+    const int64_t base = blockIdx.x * (int64_t)SCAN_TILE;
+    int s = 0;
+#pragma unroll
+    for (int k = 0; k < SCAN_ITEMS; ++k) {
+        const int64_t idx = base + k * LJ_BLOCK + threadIdx.x;
+        s += idx < m ? in[idx] : 0;
+    }
+    s = block_sum(s, lds);
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(LJ_BLOCK) void k_scan_tiles(int32_t* __restrict__ in,
+                                                         int32_t* __restrict__ out, int64_t m,
+                                                         const int32_t* __restrict__ tile_sums,
+                                                         int clear_in) {
+    __shared__ int lds[LJ_WAVES_PER_BLOCK];
+    // offset of this tile: the sums of the tiles before it
+    int before = 0;
+    for (int t = threadIdx.x; t < (int)blockIdx.x; t += LJ_BLOCK) before += tile_sums[t];
+    before = block_sum(before, lds);
     const int64_t base = blockIdx.x * (int64_t)SCAN_TILE + threadIdx.x * (int64_t)SCAN_ITEMS;
     int v[SCAN_ITEMS];
     int s = 0;
@@ -147,35 +185,13 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_scan_tile(int32_t* __restrict__ in
             if (base + k < m) in[base + k] = 0;
     }
     int total;
-    int run = block_exclusive_scan(s, lds, total);
+    int run = before + block_exclusive_scan(s, lds, total);
 #pragma unroll
     for (int k = 0; k < SCAN_ITEMS; ++k) {
         if (base + k < m) out[base + k] = run;
         run += v[k];
     }
-    if (threadIdx.x == 0) tile_sums[blockIdx.x] = total;
-}
-
-// Scans up to SCAN_TILE tile sums in place (exclusive) and writes the total.
-__global__ __launch_bounds__(LJ_BLOCK) void k_scan_sums(int32_t* __restrict__ sums, int64_t nt,
-                                                        int32_t* __restrict__ out_total) {
-    __shared__ int lds[LJ_WAVES_PER_BLOCK];
-    const int64_t base = threadIdx.x * (int64_t)SCAN_ITEMS;
-    int v[SCAN_ITEMS];
-    int s = 0;
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        v[k] = (base + k < nt) ? sums[base + k] : 0;
-        s += v[k];
-    }
-    int total;
-    int run = block_exclusive_scan(s, lds, total);
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        if (base + k < nt) sums[base + k] = run;
-        run += v[k];
-    }
-    if (threadIdx.x == 0) *out_total = total;
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[m] = before + total;
 }
 
 // Small arrays: one block.  The array is loaded with coalesced loads (all of
@@ -248,13 +264,6 @@ __global__ __launch_bounds__(SCAN1_THREADS) void k_scan_single(int32_t* __restri
     if (t == 0) out[m] = tot;
 }
 
-__global__ __launch_bounds__(LJ_BLOCK) void k_scan_add(int32_t* __restrict__ out, int64_t m,
-                                                       const int32_t* __restrict__ sums) {
-    const int add = sums[blockIdx.x];
-    const int64_t base = blockIdx.x * (int64_t)SCAN_TILE;
-    for (int k = threadIdx.x; k < SCAN_TILE; k += LJ_BLOCK)
-        if (base + k < m) out[base + k] += add;
-}
 
 inline unsigned grid_for(int64_t n, int per_block) {
     return (unsigned)((n + per_block - 1) / per_block);
@@ -285,11 +294,10 @@ lj_status lj_launch_scan(hipStream_t s, int32_t* in, int32_t* out, int64_t m, in
         LJ_HIP(hipGetLastError());
         return LJ_OK;
     }
-    hipLaunchKernelGGL(k_scan_tile, dim3((unsigned)nt), dim3(LJ_BLOCK), 0, s, in, out, m, work,
-                       clear_in ? 1 : 0);
-    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(LJ_BLOCK), 0, s, work, nt, out + m);
-    hipLaunchKernelGGL(k_scan_add, dim3((unsigned)nt), dim3(LJ_BLOCK), 0, s, out, m,
-                       (const int32_t*)work);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nt), dim3(LJ_BLOCK), 0, s,
+                       (const int32_t*)in, m, work);
+    hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(LJ_BLOCK), 0, s, in, out, m,
+                       (const int32_t*)work, clear_in ? 1 : 0);
     LJ_HIP(hipGetLastError());
     return LJ_OK;
 }

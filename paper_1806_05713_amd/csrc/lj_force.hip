@@ -134,10 +134,22 @@ __global__ __launch_bounds__(1024) void k_force_reduce(const double* __restrict_
     const int64_t b1 = (sy.slice0 + sy.nslices) / LJ_WAVES_PER_BLOCK;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double se = 0.0, sw = 0.0, sc = 0.0;
-    for (int64_t b = b0 + threadIdx.x; b < b1; b += 1024) {
-        se += partials[4 * b + 0];
-        sw += partials[4 * b + 1];
-        sc += partials[4 * b + 2];
+    // four blocks per thread and pass, loaded before they are added (the
+    // order of the sums is fixed by the thread and the pass)
+    for (int64_t bb = b0 + threadIdx.x; bb < b1; bb += 4 * 1024) {
+        double4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t b = bb + u * 1024;
+            v[u] = b < b1 ? reinterpret_cast<const double4*>(partials)[b]
+                          : make_double4(0.0, 0.0, 0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            se += v[u].x;
+            sw += v[u].y;
+            sc += v[u].z;
+        }
     }
     se = wave_sum(se);
     sw = wave_sum(sw);

@@ -130,6 +130,7 @@ struct lj_cells {
 };
 
 struct lj_list {
+    int device;                    // device of the context that built it
     int nsys;
     int64_t n;
     int kind;
@@ -145,6 +146,7 @@ struct lj_list {
     int32_t* slice_stats;          // 2 * nslices: longest row before clamping, entries
     int32_t* col;                  // ncol
     lj_list_stats* stats;          // device, nsys
+    bool stats_stale;              // stats predate the latest build
     lj_fconst* fc;                 // device, nsys: force constants of the last lj_forces*
     std::vector<lj_fconst> hfc;    // host copy of fc
     bool fc_valid;
@@ -164,8 +166,11 @@ lj_status lj_hip_fail(hipError_t e, const char* what);
 // cells (lj_cells.hip)
 lj_status lj_launch_cells(lj_ctx* ctx, const double* pos, int layout, lj_cells* c);
 int64_t lj_scan_workspace(int64_t m);
-// neighbor list (lj_neigh.hip): rebuild every system of l from cells c
-lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l);
+// neighbor list (lj_neigh.hip): rebuild every system of l from cells c; the
+// per-system statistics (longest row, entries) follow at once with `stats`,
+// else when they are next asked for (lj_launch_list_stats)
+lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l, bool stats);
+lj_status lj_launch_list_stats(hipStream_t s, lj_list* l);
 // lanes per row the list build of a new list uses (tuning knob, <= lanes)
 int lj_build_lanes(const lj_ctx* ctx, int lanes);
 // forces (lj_force.hip): per-system energy, virial, pair count

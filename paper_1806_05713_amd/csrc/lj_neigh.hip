@@ -46,6 +46,7 @@ struct NeighArgs {
     int32_t* slice_iters;
     int32_t* slice_stats;  // 2 per slice: longest row before clamping, entries stored
     int32_t* col;
+    lj_dev_status* st;     // a row that overflows its capacity raises a flag here
 };
 
 __device__ __forceinline__ double r2_rounded(double x, double y, double z) {
@@ -336,6 +337,7 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
     if (g == 0) {
         a.row_atom[R] = row_ok ? self : 0;
         a.row_len[R] = row_ok ? len : 0;
+        if (cnt > cap) atomicOr(&a.st->flags, LJ_DEV_ROW_OVERFLOW);   // rare: no contention
     }
     if ((lane % SL) == 0) {
         a.slice_iters[slice] = iters;
@@ -345,18 +347,28 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
 }
 
 // One block per system: longest row and entries over the system's slices, in
-// a fixed order, and the overflow flag of the context when a row did not fit.
+// a fixed order (the list build itself raises the overflow flag).
 __global__ __launch_bounds__(1024) void k_list_stats(const int32_t* __restrict__ slice_stats,
-                                                     const lj_sys* sys, lj_list_stats* stats,
-                                                     lj_dev_status* st) {
+                                                     const lj_sys* sys, lj_list_stats* stats) {
     __shared__ int smax[16];
     __shared__ unsigned long long ssum[16];
     const lj_sys& sy = sys[blockIdx.x];
     int mx = 0;
     unsigned long long tot = 0;
-    for (int64_t k = sy.slice0 + threadIdx.x; k < sy.slice0 + sy.nslices; k += 1024) {
-        mx = max(mx, slice_stats[2 * k]);
-        tot += (unsigned long long)slice_stats[2 * k + 1];
+    // four slices per thread and pass, loaded before they are combined
+    const int64_t end = sy.slice0 + sy.nslices;
+    for (int64_t k0 = sy.slice0 + threadIdx.x; k0 < end; k0 += 4 * 1024) {
+        int2 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t k = k0 + u * 1024;
+            v[u] = k < end ? reinterpret_cast<const int2*>(slice_stats)[k] : make_int2(0, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            mx = max(mx, v[u].x);
+            tot += (unsigned long long)v[u].y;
+        }
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
@@ -378,7 +390,6 @@ __global__ __launch_bounds__(1024) void k_list_stats(const int32_t* __restrict__
         }
         stats[blockIdx.x].max_row = mx;
         stats[blockIdx.x].entries = tot;
-        if (mx > sy.cap) atomicOr(&st->flags, LJ_DEV_ROW_OVERFLOW);
     }
 }
 
@@ -414,7 +425,7 @@ int lj_build_lanes(const lj_ctx* ctx, int lanes) {
     return gb > lanes ? lanes : gb;
 }
 
-lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l) {
+lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l, bool stats) {
     NeighArgs a;
     a.nslices = l->nslices;
     a.sys = l->dsys;
@@ -426,6 +437,7 @@ lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l) {
     a.slice_iters = l->slice_iters;
     a.slice_stats = l->slice_stats;
     a.col = l->col;
+    a.st = ctx->st;
     bool anyfull = false;
     for (const lj_sys& sy : l->hsys) anyfull = anyfull || sy.full[0] || sy.full[1] || sy.full[2];
     const bool half = l->kind == LJ_LIST_HALF;
@@ -447,9 +459,18 @@ lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l) {
     }
 #undef LJ_GB
     if (st) return st;
+    if (!stats) {
+        l->stats_stale = true;
+        return LJ_OK;
+    }
     lj_prof_scope prof(ctx, LJ_PROF_OTHER);
-    hipLaunchKernelGGL(k_list_stats, dim3((unsigned)l->nsys), dim3(1024), 0, ctx->stream,
-                       (const int32_t*)l->slice_stats, (const lj_sys*)l->dsys, l->stats, ctx->st);
+    return lj_launch_list_stats(ctx->stream, l);
+}
+
+lj_status lj_launch_list_stats(hipStream_t s, lj_list* l) {
+    hipLaunchKernelGGL(k_list_stats, dim3((unsigned)l->nsys), dim3(1024), 0, s,
+                       (const int32_t*)l->slice_stats, (const lj_sys*)l->dsys, l->stats);
     LJ_HIP(hipGetLastError());
+    l->stats_stale = false;
     return LJ_OK;
 }

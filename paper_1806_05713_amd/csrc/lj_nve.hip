@@ -219,7 +219,7 @@ lj_status enqueue_step(lj_nve* s, bool rebuild) {
     if (rebuild) {
         lj_list* l = s->list;
         if ((st = lj_launch_cells(ctx, s->pos, s->layout, l->cells))) return st;
-        if ((st = lj_launch_neighbors(ctx, l->cells, l))) return st;
+        if ((st = lj_launch_neighbors(ctx, l->cells, l, false))) return st;
     }
     if ((st = forces(s))) return st;
     hipLaunchKernelGGL(k_kick<LAYOUT>, grid, block, 0, ctx->stream, row_args(s), 0.5 * s->dt);
