@@ -29,7 +29,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
-FP64_VECTOR_TFLOPS = 78.6  # MI355X FP64 vector peak
+FP64_VECTOR_TFLOPS = 78.6  # MI355X FP64 vector peak (fused multiply-adds counted as 2)
+# FP64 vector operations per second without fusion: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz.  The exact pair test forms r^2 from separately rounded
+# products and sums, so no multiply-add can be fused and this is its ceiling.
+FP64_VALU_OPS_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
+TEST_FP64_OPS = 8          # per candidate pair test: 3 differences, 3 squares, 2 sums
 COPY_BYTES = 256 << 20     # size of the calibration copy (read once, written once)
 
 
@@ -40,10 +45,11 @@ def algorithmic_force_bytes(n: int, entries: int) -> int:
     return n * (32 + 32 + 8) + 4 * entries
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_force_lj131k_hbm_traffic.txt")
+def traffic_file(kernel: str) -> str:
+    return os.path.join(ROOT, "profiles", f"{kernel}_lj131k_hbm_traffic.txt")
 
 
-def measured_traffic(path: str = TRAFFIC_FILE):
+def measured_traffic(path: str):
     """HBM bytes per force launch from the committed counter summary (two
     rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE, scaled by a plain copy),
     or None when the summary is missing or the force-kernel sources have
@@ -196,16 +202,29 @@ def main():
 
     force_us = per["force"]
     neigh_us = per["neigh"]
+    default_shape = args.lanes in (0, 8) and args.build_lanes in (0, 4)
     bytes_force = algorithmic_force_bytes(s.n, desc.entries)
     force_gbs = bytes_force / (force_us * 1e-6) / 1e9
-    roofline = {"kernel": "k_force (FP64, full list)" if kind == lj.LJ_LIST_FULL
-                else "k_force (FP64, half list)",
-                "bound": "hbm", "achieved": round(force_gbs, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(force_gbs / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic() if (kind == lj.LJ_LIST_FULL and args.lanes in (0, 8))
-                else None,
-                "bytes_per_launch": bytes_force, "us_per_launch": round(force_us, 3)}
+    roofline_force = {
+        "kernel": "k_force (FP64, full list)" if kind == lj.LJ_LIST_FULL
+        else "k_force (FP64, half list)",
+        "bound": "hbm", "achieved": round(force_gbs, 1), "peak": HBM_PEAK_GBS,
+        "unit": "GB/s", "frac": round(force_gbs / HBM_PEAK_GBS, 4),
+        "traffic": measured_traffic(traffic_file("k_force"))
+        if (kind == lj.LJ_LIST_FULL and default_shape) else None,
+        "bytes_per_launch": bytes_force, "us_per_launch": round(force_us, 3)}
+    # the list build: bound by vector-ALU issue; its algorithmic work is the
+    # exact FP64 distance test of every candidate pair it examines
+    neigh_tflops = TEST_FP64_OPS * desc.tests / (neigh_us * 1e-6) / 1e12
+    roofline_neigh = {
+        "kernel": "k_neigh (list build, FP64 exact pair tests)",
+        "bound": "alu", "achieved": round(neigh_tflops, 3), "peak": round(FP64_VALU_OPS_PEAK_T, 2),
+        "unit": "TFLOP/s", "frac": round(neigh_tflops / FP64_VALU_OPS_PEAK_T, 4),
+        "traffic": measured_traffic(traffic_file("k_neigh"))
+        if (kind == lj.LJ_LIST_FULL and default_shape) else None,
+        "candidate_tests_per_launch": int(desc.tests), "us_per_launch": round(neigh_us, 3)}
     dominant = "force" if force_us >= neigh_us else "neigh"
+    roofline = roofline_force if dominant == "force" else roofline_neigh
 
     variants = {}
     if not args.no_variants:
@@ -244,10 +263,13 @@ def main():
                                "binning + list rebuild + forces/energy/virial",
                    "atoms": s.n, "list": args.kind, "lanes": desc.lanes, "layout": "aos4",
                    "order": "lattice", "precision": "fp64",
-                   "list_entries": desc.entries, "interacting_pairs": npairs},
+                   "list_entries": desc.entries, "candidate_tests": int(desc.tests),
+                   "interacting_pairs": npairs},
         "kernel_us": {k: round(v, 3) for k, v in per.items()},
         "dominant_kernel": dominant,
         "roofline": roofline,
+        "roofline_force": roofline_force,
+        "roofline_neigh": roofline_neigh,
         "force_only": {"us": round(ms_force_only * 1e3, 3),
                        "pairs_per_s": round(npairs / (ms_force_only * 1e-3), 1),
                        "alg_GBps": round(bytes_force / (ms_force_only * 1e-3) / 1e9, 1)},

@@ -106,6 +106,8 @@ typedef struct {
     double box[3];        /* box it was built in (system 0 of a batch) */
     int32_t nc[3];        /* cells per dimension used by the search (system 0) */
     int32_t nsys;         /* systems in the list (1 unless built as a batch) */
+    int32_t pad;
+    int64_t tests;        /* candidate pairs the latest build tested (distance tests) */
 } lj_list_desc;
 
 /* ---------------------------------------------------------------- context */

@@ -318,7 +318,7 @@ lj_status alloc_rows(lj_list* l, hipStream_t stream) {
     lj_status st;
     if ((st = dmalloc(&l->slice_sys, l->nslices)) || (st = dmalloc(&l->row_atom, rows)) ||
         (st = dmalloc(&l->row_len, rows)) || (st = dmalloc(&l->slice_iters, l->nslices)) ||
-        (st = dmalloc(&l->slice_stats, 2 * l->nslices)) || (st = dmalloc(&l->stats, l->nsys)) ||
+        (st = dmalloc(&l->slice_stats, l->nslices)) || (st = dmalloc(&l->stats, l->nsys)) ||
         (st = dmalloc(&l->dsys, l->nsys)) || (st = dmalloc(&l->fc, l->nsys)))
         return st;
     std::vector<int32_t> ss((size_t)l->nslices);
@@ -710,11 +710,14 @@ extern "C" lj_status lj_list_info(const lj_list* l, lj_list_desc* out) {
     out->cap = 0;
     out->max_row = 0;
     out->entries = 0;
+    out->tests = 0;
     for (int s = 0; s < l->nsys; ++s) {
         out->cap = out->cap > l->hsys[(size_t)s].cap ? out->cap : l->hsys[(size_t)s].cap;
         out->max_row = out->max_row > h[(size_t)s].max_row ? out->max_row : h[(size_t)s].max_row;
         out->entries += (int64_t)h[(size_t)s].entries;
+        out->tests += (int64_t)h[(size_t)s].tests;
     }
+    out->pad = 0;
     out->slots = l->ncol;
     out->rc = l->hsys[0].rc_list;
     out->skin = l->hsys[0].skin;

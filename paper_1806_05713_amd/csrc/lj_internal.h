@@ -84,6 +84,7 @@ struct lj_list_stats {
     int32_t max_row;               // longest row (before clamping to the capacity)
     int32_t pad;
     unsigned long long entries;    // entries stored
+    unsigned long long tests;      // candidate pairs tested by the build
 };
 
 struct lj_prof_rec {
@@ -143,7 +144,8 @@ struct lj_list {
     int32_t* row_atom;             // nslices * C
     int32_t* row_len;              // nslices * C
     int32_t* slice_iters;          // nslices
-    int32_t* slice_stats;          // 2 * nslices: longest row before clamping, entries
+    int4* slice_stats;             // nslices: longest row before clamping, entries,
+                                   // candidates tested, unused
     int32_t* col;                  // ncol
     lj_list_stats* stats;          // device, nsys
     bool stats_stale;              // stats predate the latest build

@@ -44,7 +44,8 @@ struct NeighArgs {
     int32_t* row_atom;
     int32_t* row_len;
     int32_t* slice_iters;
-    int32_t* slice_stats;  // 2 per slice: longest row before clamping, entries stored
+    int4* slice_stats;     // per slice: longest row before clamping, entries stored,
+                           // candidates tested, unused
     int32_t* col;
     lj_dev_status* st;     // a row that overflows its capacity raises a flag here
 };
@@ -143,6 +144,7 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
     const uint64_t grp = (GB == LJ_WAVE) ? ~0ull : (((1ull << (GB & 63)) - 1ull) << (cb * GB));
     const uint32_t grp_lo = (uint32_t)grp, grp_hi = (uint32_t)(grp >> 32);
     int cnt = 0;
+    int tests = 0;   // candidates this row tested
 
     // pair test of candidate rank s with record qj; x shifted by shx if shifted_x
     auto test_q = [&](const double4& qj, int s, double shx, double shy, double shz,
@@ -303,6 +305,7 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
         const int b0 = group_bcast<GB, Q>(mine.b0), b1 = group_bcast<GB, Q>(mine.b1);
         const double shy = group_bcast<GB, Q>(mine.shy), shz = group_bcast<GB, Q>(mine.shz);
         const double shb = group_bcast<GB, Q>(mine.shb);
+        tests += (a1 - a0) + (b1 - b0);
         scan(a0, a1 - a0, 0.0, shy, shz, false);
         scan(b0, b1 - b0, shb, shy, shz, true);
     };
@@ -324,12 +327,13 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
 
     const int len = cnt < cap ? cnt : cap;
     // longest row and entries of each slice (its SL lanes; no atomics)
-    int mx = len, over = cnt, tot = (g == 0) ? len : 0;
+    int mx = len, over = cnt, tot = (g == 0) ? len : 0, ntest = (g == 0) ? tests : 0;
 #pragma unroll
     for (int d = SL / 2; d >= 1; d >>= 1) {
         mx = max(mx, __shfl_xor(mx, d, LJ_WAVE));
         over = max(over, __shfl_xor(over, d, LJ_WAVE));
         tot += __shfl_xor(tot, d, LJ_WAVE);
+        ntest += __shfl_xor(ntest, d, LJ_WAVE);
     }
     const int iters = (mx + G - 1) / G;
     // pad the row up to the slice length with the row's own atom
@@ -341,55 +345,60 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
     }
     if ((lane % SL) == 0) {
         a.slice_iters[slice] = iters;
-        a.slice_stats[2 * slice] = over;
-        a.slice_stats[2 * slice + 1] = tot;
+        a.slice_stats[slice] = make_int4(over, tot, ntest, 0);
     }
 }
 
 // One block per system: longest row and entries over the system's slices, in
 // a fixed order (the list build itself raises the overflow flag).
-__global__ __launch_bounds__(1024) void k_list_stats(const int32_t* __restrict__ slice_stats,
+__global__ __launch_bounds__(1024) void k_list_stats(const int4* __restrict__ slice_stats,
                                                      const lj_sys* sys, lj_list_stats* stats) {
     __shared__ int smax[16];
-    __shared__ unsigned long long ssum[16];
+    __shared__ unsigned long long ssum[16], stest[16];
     const lj_sys& sy = sys[blockIdx.x];
     int mx = 0;
-    unsigned long long tot = 0;
+    unsigned long long tot = 0, tst = 0;
     // four slices per thread and pass, loaded before they are combined
     const int64_t end = sy.slice0 + sy.nslices;
     for (int64_t k0 = sy.slice0 + threadIdx.x; k0 < end; k0 += 4 * 1024) {
-        int2 v[4];
+        int4 v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t k = k0 + u * 1024;
-            v[u] = k < end ? reinterpret_cast<const int2*>(slice_stats)[k] : make_int2(0, 0);
+            v[u] = k < end ? slice_stats[k] : make_int4(0, 0, 0, 0);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             mx = max(mx, v[u].x);
             tot += (unsigned long long)v[u].y;
+            tst += (unsigned long long)v[u].z;
         }
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         mx = max(mx, __shfl_xor(mx, d, LJ_WAVE));
         tot += __shfl_xor(tot, d, LJ_WAVE);
+        tst += __shfl_xor(tst, d, LJ_WAVE);
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) {
         smax[wave] = mx;
         ssum[wave] = tot;
+        stest[wave] = tst;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         mx = 0;
         tot = 0;
+        tst = 0;
         for (int w = 0; w < 16; ++w) {
             mx = max(mx, smax[w]);
             tot += ssum[w];
+            tst += stest[w];
         }
         stats[blockIdx.x].max_row = mx;
         stats[blockIdx.x].entries = tot;
+        stats[blockIdx.x].tests = tst;
     }
 }
 
@@ -469,7 +478,7 @@ lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l, bool s
 
 lj_status lj_launch_list_stats(hipStream_t s, lj_list* l) {
     hipLaunchKernelGGL(k_list_stats, dim3((unsigned)l->nsys), dim3(1024), 0, s,
-                       (const int32_t*)l->slice_stats, (const lj_sys*)l->dsys, l->stats);
+                       (const int4*)l->slice_stats, (const lj_sys*)l->dsys, l->stats);
     LJ_HIP(hipGetLastError());
     l->stats_stale = false;
     return LJ_OK;

@@ -59,7 +59,8 @@ class ListDesc(ctypes.Structure):
                 ("cap", ctypes.c_int32), ("max_row", ctypes.c_int32),
                 ("entries", ctypes.c_int64), ("slots", ctypes.c_int64),
                 ("rc", ctypes.c_double), ("skin", ctypes.c_double),
-                ("box", ctypes.c_double * 3), ("nc", ctypes.c_int32 * 3), ("nsys", ctypes.c_int32)]
+                ("box", ctypes.c_double * 3), ("nc", ctypes.c_int32 * 3), ("nsys", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("tests", ctypes.c_int64)]
 
 
 _lib = None
