@@ -161,6 +161,7 @@ void list_release(lj_list* l) {
     dfree(l->row_len);
     dfree(l->slice_iters);
     dfree(l->slice_stats);
+    dfree(l->acc);
     dfree(l->col);
     dfree(l->stats);
     dfree(l->fc);
@@ -321,6 +322,13 @@ lj_status alloc_rows(lj_list* l, hipStream_t stream) {
         (st = dmalloc(&l->slice_stats, l->nslices)) || (st = dmalloc(&l->stats, l->nsys)) ||
         (st = dmalloc(&l->dsys, l->nsys)) || (st = dmalloc(&l->fc, l->nsys)))
         return st;
+    if (l->kind == LJ_LIST_HALF) {
+        // the half list's spread force accumulator, zero between force calls
+        const int64_t words = 3 * 16 * ((l->n + 15) / 16);
+        if ((st = dmalloc(&l->acc, words)) ||
+            (st = lj_launch_zero(stream, l->acc, words * (int64_t)sizeof(double))))
+            return st;
+    }
     std::vector<int32_t> ss((size_t)l->nslices);
     for (int s = 0; s < l->nsys; ++s)
         for (int64_t t = 0; t < l->hsys[s].nslices; ++t) ss[(size_t)(l->hsys[s].slice0 + t)] = s;

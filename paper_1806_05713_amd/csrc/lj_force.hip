@@ -38,6 +38,8 @@ struct ForceArgs {
     const int32_t* slice_iters;
     const int32_t* col;
     double* partials;        // 4 doubles per (logical) block
+    double* acc;             // half list: spread force accumulator (3 x 16 n16 doubles)
+    int64_t n16;
 };
 
 __device__ __forceinline__ double r2_rounded(double x, double y, double z) {
@@ -72,6 +74,18 @@ __device__ __forceinline__ void add_f(double* __restrict__ f, int64_t n, int64_t
         unsafeAtomicAdd(f + n + i, y);
         unsafeAtomicAdd(f + 2 * n + i, z);
     }
+}
+
+// Half list: the Newton's-third-law scatter goes into an accumulator with
+// one block per component, so that the three atomics of a pair do not queue
+// on one cache line.
+__device__ __forceinline__ int64_t spread_at(int64_t i, int64_t n16) { return i; }
+__device__ __forceinline__ void acc_add(double* __restrict__ acc, int64_t n16, int64_t i,
+                                        double x, double y, double z) {
+    const int64_t s = spread_at(i, n16);
+    unsafeAtomicAdd(acc + s, x);
+    unsafeAtomicAdd(acc + 16 * n16 + s, y);
+    unsafeAtomicAdd(acc + 32 * n16 + s, z);
 }
 
 template <int LAYOUT>
@@ -285,7 +299,7 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_force(ForceArgs a) {
             fx = fma(-fs, tx, fx);
             fy = fma(-fs, ty, fy);
             fz = fma(-fs, tz, fz);
-            if (HALF && m) add_f<LAYOUT>(a.force, a.n, jc[u], fs * tx, fs * ty, fs * tz);
+            if (HALF && m) acc_add(a.acc, a.n16, jc[u], fs * tx, fs * ty, fs * tz);
         }
     }
     // sum the row over its G lanes
@@ -297,12 +311,27 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_force(ForceArgs a) {
     }
     if (g == 0 && row_ok) {
         if (HALF)
-            add_f<LAYOUT>(a.force, a.n, i, fx, fy, fz);
+            acc_add(a.acc, a.n16, i, fx, fy, fz);
         else
             store_f<LAYOUT>(a.force, a.n, i, fx, fy, fz);
     }
     // per lane: 4 eps (A - B) and 24 eps (2A - B)
     block_partials(a, blk, fc.c4 * (sA - sB), fc.c24 * (2.0 * sA - sB), (double)cnt);
+}
+
+// Half list: the forces from the spread accumulator, which is cleared for
+// the next evaluation.
+template <int LAYOUT>
+__global__ __launch_bounds__(LJ_BLOCK) void k_acc_out(double* __restrict__ acc, int64_t n16,
+                                                      int64_t n, double* __restrict__ f) {
+    const int64_t i = blockIdx.x * (int64_t)LJ_BLOCK + threadIdx.x;
+    if (i >= n) return;
+    const int64_t s = spread_at(i, n16);
+    const double x = acc[s], y = acc[16 * n16 + s], z = acc[32 * n16 + s];
+    acc[s] = 0.0;
+    acc[16 * n16 + s] = 0.0;
+    acc[32 * n16 + s] = 0.0;
+    store_f<LAYOUT>(f, n, i, x, y, z);
 }
 
 template <int G, int U>
@@ -358,12 +387,7 @@ lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int preci
     const int64_t blocks = lj_force_blocks(l->nslices);
     if (blocks > ctx->partials_cap) return lj_fail(LJ_E_INVALID, "context partials too small");
     const bool half = l->kind == LJ_LIST_HALF;
-    if (half) {
-        lj_prof_scope prof(ctx, LJ_PROF_OTHER);
-        const int64_t bytes = (int64_t)sizeof(double) * (layout == LJ_AOS4 ? 4 : 3) * l->n;
-        lj_status st = lj_launch_zero(ctx->stream, force, bytes);
-        if (st) return st;
-    }
+    if (half && !l->acc) return lj_fail(LJ_E_INVALID, "half list without its force accumulator");
     ForceArgs a;
     a.pos = pos;
     a.force = force;
@@ -377,6 +401,8 @@ lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int preci
     a.slice_iters = l->slice_iters;
     a.col = l->col;
     a.partials = ctx->partials;
+    a.acc = l->acc;
+    a.n16 = (l->n + 15) / 16;
     lj_status st;
     {
         lj_prof_scope prof(ctx, LJ_PROF_FORCE);
@@ -400,6 +426,16 @@ lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int preci
     }
     if (st) return st;
     lj_prof_scope prof(ctx, LJ_PROF_OTHER);
+    if (half) {
+        const dim3 grid((unsigned)((l->n + LJ_BLOCK - 1) / LJ_BLOCK)), block(LJ_BLOCK);
+        if (layout == LJ_AOS4)
+            hipLaunchKernelGGL(k_acc_out<LJ_AOS4>, grid, block, 0, ctx->stream, l->acc, a.n16,
+                               l->n, force);
+        else
+            hipLaunchKernelGGL(k_acc_out<LJ_SOA>, grid, block, 0, ctx->stream, l->acc, a.n16,
+                               l->n, force);
+        LJ_HIP(hipGetLastError());
+    }
     hipLaunchKernelGGL(k_force_reduce, dim3((unsigned)l->nsys), dim3(1024), 0, ctx->stream,
                        (const double*)ctx->partials, (const lj_sys*)l->dsys, fc,
                        half ? 1.0 : 0.5, energy, virial, npairs);

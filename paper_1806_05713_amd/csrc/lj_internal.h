@@ -153,6 +153,7 @@ struct lj_list {
     std::vector<lj_fconst> hfc;    // host copy of fc
     bool fc_valid;
     lj_cells* cells;               // owned cell structure for in-place rebuilds (lazy)
+    double* acc;                   // half list: spread force accumulator, zero between calls
 };
 
 // ---------------------------------------------------------------- errors
