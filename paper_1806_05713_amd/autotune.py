@@ -100,6 +100,49 @@ def tune(ctx, pos, box, rc, skin, kind=lj.LJ_LIST_FULL, precision=lj.LJ_FP64,
     return {"best": {k: best[k] for k in names}, "objective": objective, "results": results}
 
 
+def measure_batch(ctx, pos, n, box, rc, skin, kind, precision, cfg, reps: int = 10) -> dict:
+    """Device time (us) of one batched list rebuild and one batched force
+    evaluation with cfg (eps = sigma = 1 for every system)."""
+    import numpy as np
+    import torch
+    apply(ctx, cfg)
+    nl = lj.lj_build_neighbors_batch(ctx, pos, n, box, rc, skin, kind=kind, lanes=cfg["lanes"])
+    ones = np.ones(len(n))
+    force = torch.empty_like(pos)
+    for _ in range(2):
+        lj.lj_update_neighbors(ctx, pos, None, nl)
+        lj.lj_forces_batch(ctx, pos, nl, ones, ones, rc, precision, force)
+    ctx.profile_begin()
+    for _ in range(reps):
+        lj.lj_update_neighbors(ctx, pos, None, nl)
+        lj.lj_forces_batch(ctx, pos, nl, ones, ones, rc, precision, force)
+    prof = ctx.profile_end()
+    ctx.sync()
+    nl.free()
+    per = {k: v[0] * 1e3 / max(v[1], 1) for k, v in prof.items()}
+    return {"build_us": per["cells"] + per["neigh"], "force_us": per["force"],
+            "step_us": per["cells"] + per["neigh"] + per["force"] + per["other"]}
+
+
+def tune_batch(ctx, pos, n, box, rc, skin, kind=lj.LJ_LIST_FULL, precision=lj.LJ_FP64,
+               objective: str = "step_us", space: Optional[dict] = None, reps: int = 10,
+               log=None) -> dict:
+    """tune() for a batch of systems (lj_build_neighbors_batch / lj_forces_batch)."""
+    space = dict(SPACE if space is None else space)
+    results = []
+    names = list(space)
+    for vals in itertools.product(*(space[k] for k in names)):
+        cfg = dict(zip(names, vals))
+        if cfg.get("build_lanes", 1) > cfg["lanes"]:
+            continue
+        t = measure_batch(ctx, pos, n, box, rc, skin, kind, precision, cfg, reps)
+        results.append({**cfg, **t})
+        if log:
+            log(json.dumps(results[-1]))
+    best = min(results, key=lambda r: r[objective])
+    return {"best": {k: best[k] for k in names}, "objective": objective, "results": results}
+
+
 def best_config(ctx, pos, box, rc, skin, kind, precision, rho: float,
                 cache_path: str = CACHE, retune: bool = False, log=None) -> dict:
     """Cached tuned configuration for this device and workload shape."""

@@ -88,7 +88,7 @@ def load(path: str = LIB_PATH):
         "lj_cells_export": ([_VP, _VP, _VP, _VP]),
         "lj_cells_free": ([_VP]),
         "lj_build_neighbors": ([_VP, _VP, i64, i32, _D3, dbl, dbl, i32, i32, _VP, PP]),
-        "lj_update_neighbors": ([_VP, _VP, i64, i32, _D3, _VP]),
+        "lj_update_neighbors": ([_VP, _VP, i64, i32, ctypes.POINTER(ctypes.c_double), _VP]),
         "lj_list_info": ([_VP, ctypes.POINTER(ListDesc)]),
         "lj_profile_begin": ([_VP]),
         "lj_profile_end": ([_VP, _VP, _VP]),
@@ -299,9 +299,11 @@ def lj_build_neighbors(ctx: Context, pos, box, rc: float, skin: float,
 
 
 def lj_update_neighbors(ctx: Context, pos, box, nlist: NeighborList) -> NeighborList:
-    """Rebuild nlist in place for new positions (asynchronous)."""
+    """Rebuild nlist in place for new positions (asynchronous).  box may be
+    None for a batch list (each system keeps its own box)."""
     n, layout = _pos_layout(pos)
-    _check(load().lj_update_neighbors(ctx.h, _ptr(pos), n, layout, _box(box), nlist.h),
+    _check(load().lj_update_neighbors(ctx.h, _ptr(pos), n, layout,
+                                      None if box is None else _box(box), nlist.h),
            "lj_update_neighbors")
     return nlist
 

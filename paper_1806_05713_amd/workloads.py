@@ -127,6 +127,17 @@ def bench_batch512(steps: int = 100, warmup: int = 0, cpu: bool = False):
     pos0 = np.concatenate([x.pos for x in systems])
     vel0 = np.concatenate([x.vel for x in systems])
     ctx = lj.Context(0, stream=torch.cuda.Stream())
+    # launch shapes for this batch from the autotuner (timed on the batch itself)
+    from . import autotune
+    with torch.cuda.stream(ctx.stream):
+        pos = torch.from_numpy(synth.aos4(pos0)).to(dev)
+        torch.cuda.synchronize()
+        tuned = autotune.tune_batch(ctx, pos, n, box, rc, 0.3,
+                                    space={"lanes": (4, 8), "build_lanes": (2, 4),
+                                           "batch": (2, 4), "cell_div": (2,)}, reps=5)
+    best = tuned["best"]
+    autotune.apply(ctx, best)
+    _note(f"batch512: tuned {best}")
     out = {}
     for prec_name, prec in (("fp64", lj.LJ_FP64), ("mixed", lj.LJ_MIXED)):
         with torch.cuda.stream(ctx.stream):
@@ -134,7 +145,8 @@ def bench_batch512(steps: int = 100, warmup: int = 0, cpu: bool = False):
             vel = torch.from_numpy(synth.aos4(vel0)).to(dev)
             force = torch.zeros_like(pos)
             torch.cuda.synchronize()
-            nl = lj.lj_build_neighbors_batch(ctx, pos, n, box, rc, 0.3, kind=lj.LJ_LIST_FULL)
+            nl = lj.lj_build_neighbors_batch(ctx, pos, n, box, rc, 0.3, kind=lj.LJ_LIST_FULL,
+                                             lanes=best["lanes"])
             ms, log = _nve_run(ctx, pos, vel, force, None, ones, ones, rc, nl, 0.005, steps,
                                prec, True)
             prof = _phase_profile(ctx, pos, vel, force, None, ones, ones, rc, nl, 0.005, prec,
@@ -150,7 +162,8 @@ def bench_batch512(steps: int = 100, warmup: int = 0, cpu: bool = False):
     with torch.cuda.stream(ctx.stream):
         pos = torch.from_numpy(synth.aos4(pos0)).to(dev)
         torch.cuda.synchronize()
-        nl = lj.lj_build_neighbors_batch(ctx, pos, n, box, rc, 0.3, kind=lj.LJ_LIST_FULL)
+        nl = lj.lj_build_neighbors_batch(ctx, pos, n, box, rc, 0.3, kind=lj.LJ_LIST_FULL,
+                                         lanes=best["lanes"])
         F = torch.empty_like(pos)
         lj.lj_forces_batch(ctx, pos, nl, ones, ones, rc, force=F)
         ctx.sync()
@@ -165,7 +178,8 @@ def bench_batch512(steps: int = 100, warmup: int = 0, cpu: bool = False):
         for k, x in enumerate(systems):
             p = pos[off[k]:off[k + 1]].contiguous()
             singles.append((p, lj.lj_build_neighbors(ctx, p, x.box, x.rc, 0.3,
-                                                     kind=lj.LJ_LIST_FULL), x))
+                                                     kind=lj.LJ_LIST_FULL,
+                                                     lanes=best["lanes"]), x))
         outs = [(torch.empty_like(p), torch.empty(2, dtype=torch.float64, device=dev))
                 for p, _, _ in singles]
         ctx.sync()
@@ -187,9 +201,12 @@ def bench_batch512(steps: int = 100, warmup: int = 0, cpu: bool = False):
         "config": {"workload": "512 independent LJ systems, N ~ U{256..16384} (total "
                                f"{int(n.sum())} atoms), rho ~ U[0.7, 1.1], rc ~ U[2.5, 3.0], "
                                "skin 0.3, jittered FCC, T=1.0; one launch per phase for all "
-                               "systems, 100-step NVE as HIP-graph cycles of 10",
+                               "systems, 100-step NVE as HIP-graph cycles of 10, "
+                               "launch shapes autotuned on the batch",
                    "systems": len(systems), "atoms": int(n.sum())},
         "fp64": f64, "mixed": out["mixed"],
+        "autotuned": best,
+        "autotune_results": tuned["results"],
         "force_batched_ms": round(t_batched * 1e3, 3),
         "force_per_system_launch_loop_ms": round(t_loop * 1e3, 3),
         "batching_gain_force": round(t_loop / t_batched, 2),
