@@ -124,6 +124,9 @@ def main():
     ap.add_argument("--lanes", type=int, default=0, help="lanes per list row (0: default)")
     ap.add_argument("--build-lanes", type=int, default=0,
                     help="lanes per row in the list build, 1, 2 or 4 (0: default)")
+    ap.add_argument("--force-batch", type=int, default=0,
+                    help="list entries in flight per lane in the force kernel, 2, 4 or 8 "
+                         "(0: default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-variants", action="store_true", help="skip the variant matrix")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -167,6 +170,8 @@ def main():
     ctx = lj.Context(0)
     if args.build_lanes:
         ctx.tune_set(lj.LJ_TUNE_BUILD_LANES, args.build_lanes)
+    if args.force_batch:
+        ctx.tune_set(lj.LJ_TUNE_FORCE_BATCH, args.force_batch)
 
     s = synth.lj131k()
     kind = lj.LJ_LIST_FULL if args.kind == "full" else lj.LJ_LIST_HALF
@@ -202,7 +207,8 @@ def main():
 
     force_us = per["force"]
     neigh_us = per["neigh"]
-    default_shape = args.lanes in (0, 8) and args.build_lanes in (0, 4)
+    default_shape = (args.lanes in (0, 8) and args.build_lanes in (0, 4) and
+                     args.force_batch in (0, 4))
     bytes_force = algorithmic_force_bytes(s.n, desc.entries)
     force_gbs = bytes_force / (force_us * 1e-6) / 1e9
     roofline_force = {
