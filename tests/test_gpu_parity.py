@@ -415,3 +415,72 @@ def test_update_overflow_reported(lj, ctx):
         ctx.sync()
     assert e.value.status == lj.LJ_E_CAPACITY
     ctx.sync()   # reported once: the next sync is clean
+
+
+def test_lj500k_sampled(lj, ctx, oracle):
+    """The 500,000-atom density-1 fluid of the accuracy run (50^3 cells),
+    jittered: FP64 forces of 1,000 sampled atoms against the oracle computed
+    one by one, and the mixed kernel against the FP64 kernel over every atom
+    at 1e-5, for both kinds of list."""
+    s = synth.small_fcc(50, 1.0, 0.1, 4096, rc=3.0)
+    assert s.n == 500_000
+    pos = to_dev(s.pos, 0)
+    rng = np.random.Generator(np.random.PCG64(41))
+    idx = np.sort(rng.choice(s.n, size=1000, replace=False))
+    f_ref = oracle.sample(s.pos, s.box, 1, 1, s.rc, s.rc + s.skin, idx)[0]
+    scale = max(np.abs(f_ref).max(), 24.0)
+    for kind in (1, 0):
+        nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=kind)
+        F64, E64, W64, n64 = lj.lj_forces(ctx, pos, s.box, 1.0, 1.0, s.rc, nl, lj.LJ_FP64)
+        F32, E32, W32, n32 = lj.lj_forces(ctx, pos, s.box, 1.0, 1.0, s.rc, nl, lj.LJ_MIXED)
+        torch.cuda.synchronize()
+        f64 = F64.cpu().numpy()[:, :3]
+        f32 = F32.cpu().numpy()[:, :3]
+        assert np.abs(f64[idx] - f_ref).max() <= 1e-10 * scale
+        assert np.abs(f32 - f64).max() <= 1e-5 * max(np.abs(f64).max(), 24.0)
+        assert abs(E32.item() - E64.item()) <= 1e-6 * abs(E64.item())
+        assert abs(W32.item() - W64.item()) <= 1e-6 * abs(W64.item())
+        assert n32.item() == n64.item()
+
+
+def test_cutoffs_are_strict_on_exact_distances(lj, ctx, oracle):
+    """Pairs at exactly rs and exactly rc (and one ulp inside): a pair is listed
+    iff r^2 < rs^2 and interacts iff r^2 < rc^2, with r^2 rounded as in the
+    definition; the GPU agrees with the oracle on every one."""
+    rc, skin = 3.0, 0.3
+    rs = rc + skin
+    L = 12.0
+    pts = [
+        [1.0, 1.0, 1.0], [1.0 + rs, 1.0, 1.0],                       # r = rs: not listed
+        [1.0, 5.0, 1.0], [1.0, 5.0 + rc, 1.0],                       # r = rc: listed, no force
+        [6.0, 1.0, 7.0], [6.0 + np.nextafter(rs, 0.0), 1.0, 7.0],    # just inside rs
+        [6.0, 6.0, 5.0], [6.0, 6.0, 5.0 + np.nextafter(rc, 0.0)],    # just inside rc
+        [L - 1.5, 9.0, 9.0], [1.8, 9.0, 9.0],                        # r = rs across the face
+    ]
+    s = synth.System(pos=synth.wrap(np.array(pts), L), box=np.array([L, L, L]), rc=rc,
+                     skin=skin, name="ties")
+    ref = reference(oracle, s)
+    pos = to_dev(s.pos, 0)
+    for kind in (0, 1):
+        nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=kind)
+        ij = nl.pairs()
+        sel = ij if kind == 0 else ij[ij[:, 0] < ij[:, 1]]
+        assert np.array_equal(canon(sel), ref[0])
+        F, E, W, n = lj.lj_forces(ctx, pos, s.box, 1.0, 1.0, s.rc, nl)
+        torch.cuda.synchronize()
+        assert n.item() == ref[4]
+        check_forces(s, forces_to_np(F, 0), E.item(), W.item(), n.item(), ref)
+
+
+def test_atom_count_limit(lj, ctx):
+    """More than LJ_MAX_ATOMS atoms is refused before any device memory is
+    touched (kernels address records with 32-bit byte offsets)."""
+    import ctypes
+    L = lj.load()
+    pos = to_dev(synth.lj4k().pos, 0)
+    box = (ctypes.c_double * 3)(20.0, 20.0, 20.0)
+    out = ctypes.c_void_p()
+    st = L.lj_build_neighbors(ctx.h, pos.data_ptr(), (1 << 27) + 1, 0, box, 3.0, 0.3, 1, 0,
+                              None, ctypes.byref(out))
+    assert st == lj.LJ_E_INVALID
+    assert "LJ_MAX_ATOMS" in lj.lj_last_error()
