@@ -123,7 +123,7 @@ def main():
     ap.add_argument("--kind", choices=["full", "half"], default="full")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per list row (0: default)")
     ap.add_argument("--build-lanes", type=int, default=0,
-                    help="lanes per row in the list build, 1, 2 or 4 (0: default)")
+                    help="lanes per row in the list build, 64, 1, 2 or 4 (0: default, 64)")
     ap.add_argument("--force-batch", type=int, default=0,
                     help="list entries in flight per lane in the force kernel, 2, 4 or 8 "
                          "(0: default)")
@@ -207,7 +207,7 @@ def main():
 
     force_us = per["force"]
     neigh_us = per["neigh"]
-    default_shape = (args.lanes in (0, 8) and args.build_lanes in (0, 4) and
+    default_shape = (args.lanes in (0, 8) and args.build_lanes in (0, 64) and
                      args.force_batch in (0, 4))
     bytes_force = algorithmic_force_bytes(s.n, desc.entries)
     force_gbs = bytes_force / (force_us * 1e-6) / 1e9

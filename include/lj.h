@@ -291,9 +291,11 @@ LJ_API lj_status lj_nve_free(lj_nve* nve);
 /* Launch-shape knobs of a context, set by the autotuner (or by hand).  They
  * change only speed, never results: every setting computes the same list
  * (as a set) and the same forces.  0 selects the library's default. */
-#define LJ_TUNE_BUILD_LANES 0   /* lanes per row in the list-build kernel: 1, 2 or 4
-                                   (at most the list's lanes); default 4.  Fixed
-                                   for a list when it is created. */
+#define LJ_TUNE_BUILD_LANES 0   /* lanes per row in the list-build kernel: 64 (the
+                                   whole wavefront builds one row at a time, the
+                                   default) or 1, 2 or 4 (groups of lanes build
+                                   rows side by side, at most the list's lanes).
+                                   Fixed for a list when it is created. */
 #define LJ_TUNE_FORCE_BATCH 1   /* list entries each lane has in flight in the force
                                    kernel: 2, 4 or 8; default 4 */
 #define LJ_TUNE_CELL_DIV 2      /* lists built without caller cells use cells of side

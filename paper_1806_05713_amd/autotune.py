@@ -27,7 +27,7 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.jso
 
 SPACE = {
     "lanes": (4, 8, 16),
-    "build_lanes": (1, 2, 4),
+    "build_lanes": (64, 4, 2),
     "batch": (2, 4, 8),
     "cell_div": (1, 2, 3),
 }
@@ -90,7 +90,7 @@ def tune(ctx, pos, box, rc, skin, kind=lj.LJ_LIST_FULL, precision=lj.LJ_FP64,
     names = list(space)
     for vals in itertools.product(*(space[k] for k in names)):
         cfg = dict(zip(names, vals))
-        if cfg["build_lanes"] > cfg["lanes"]:
+        if cfg["build_lanes"] != 64 and cfg["build_lanes"] > cfg["lanes"]:
             continue
         t = measure(ctx, pos, box, rc, skin, kind, precision, cfg, reps)
         results.append({**cfg, **t})
@@ -133,7 +133,7 @@ def tune_batch(ctx, pos, n, box, rc, skin, kind=lj.LJ_LIST_FULL, precision=lj.LJ
     names = list(space)
     for vals in itertools.product(*(space[k] for k in names)):
         cfg = dict(zip(names, vals))
-        if cfg.get("build_lanes", 1) > cfg["lanes"]:
+        if cfg.get("build_lanes", 1) != 64 and cfg.get("build_lanes", 1) > cfg["lanes"]:
             continue
         t = measure_batch(ctx, pos, n, box, rc, skin, kind, precision, cfg, reps)
         results.append({**cfg, **t})

@@ -930,7 +930,9 @@ extern "C" lj_status lj_tune_set(lj_ctx* ctx, int32_t knob, int32_t value) {
     if (!ctx) return lj_fail(LJ_E_INVALID, "context is NULL");
     bool ok = false;
     switch (knob) {
-        case LJ_TUNE_BUILD_LANES: ok = value == 0 || value == 1 || value == 2 || value == 4; break;
+        case LJ_TUNE_BUILD_LANES:
+            ok = value == 0 || value == 1 || value == 2 || value == 4 || value == 64;
+            break;
         case LJ_TUNE_FORCE_BATCH: ok = value == 0 || value == 2 || value == 4 || value == 8; break;
         case LJ_TUNE_CELL_DIV: ok = value >= 0 && value <= 4; break;
         default: return lj_fail(LJ_E_INVALID, "unknown tuning knob");

@@ -64,7 +64,157 @@ __device__ __forceinline__ double nearest(double t, double L, double hL) {
 // Gap, in cells, between a point at fraction f in [0, 1) of its cell and the
 // cell at offset o (0 for the point's own cell).
 __device__ __forceinline__ float cell_gap(int o, float f) {
-    return o > 0 ? (float)o - f : (o < 0 ? f - (float)(o + 1) : 0.0f);
+    // (o - f for o > 0, f - (o + 1) for o < 0, 0 for o = 0; f in [0, 1])
+    const float of = (float)o;
+    return fmaxf(of - f, 0.0f) + fmaxf(f - of - 1.0f, 0.0f);
+}
+
+// Which (y, z) cell rows a row visits: R cells either side, or the whole
+// dimension when it has too few cells for the image to follow from the offset;
+// with the system's grid and culling constants, read once per wavefront.
+struct Stencil {
+    int ky_n, kz_n, ncombo;
+    int Rx, Ry, Rz;
+    bool fullx, fully, fullz;
+    int nx, ny, nz;
+    float inv_kyn;               // 1 / ky_n, for the combination's (y, z) offsets
+    float cs2y, cs2z, rsd2f, inv_cs2x;
+    double inv_cs[3], box[3];
+};
+
+template <bool ANYFULL>
+__device__ __forceinline__ Stencil make_stencil(const lj_sys& sy) {
+    Stencil s;
+    s.fullx = ANYFULL && sy.full[0];
+    s.fully = ANYFULL && sy.full[1];
+    s.fullz = ANYFULL && sy.full[2];
+    s.Rx = sy.reach[0];
+    s.Ry = s.fully ? 0 : sy.reach[1];
+    s.Rz = s.fullz ? 0 : sy.reach[2];
+    s.nx = sy.nc[0];
+    s.ny = sy.nc[1];
+    s.nz = sy.nc[2];
+    s.ky_n = s.fully ? s.ny : 2 * s.Ry + 1;
+    s.kz_n = s.fullz ? s.nz : 2 * s.Rz + 1;
+    s.ncombo = s.ky_n * s.kz_n;
+    s.inv_kyn = 1.0f / (float)s.ky_n;
+    s.cs2y = sy.cs2f[1];
+    s.cs2z = sy.cs2f[2];
+    s.rsd2f = sy.rsd2f;
+    s.inv_cs2x = 1.0f / sy.cs2f[0];
+    for (int d = 0; d < 3; ++d) {
+        s.inv_cs[d] = sy.inv_cs[d];
+        s.box[d] = sy.box[d];
+    }
+    return s;
+}
+
+// Cell of a row's atom and its fractional position in the cell (FP32,
+// culling only); ok = false for the padding rows past the system's atoms.
+struct RowGeo {
+    int cx, cy, cz;
+    float fx, fy, fz;
+    bool ok;
+};
+
+__device__ __forceinline__ RowGeo row_geo(const Stencil& st, const double4& q, bool ok) {
+    RowGeo g;
+    g.cx = lj_cell_coord(q.x, st.inv_cs[0], st.nx);
+    g.cy = lj_cell_coord(q.y, st.inv_cs[1], st.ny);
+    g.cz = lj_cell_coord(q.z, st.inv_cs[2], st.nz);
+    g.fx = (float)(q.x * st.inv_cs[0] - g.cx);
+    g.fy = (float)(q.y * st.inv_cs[1] - g.cy);
+    g.fz = (float)(q.z * st.inv_cs[2] - g.cz);
+    g.ok = ok;
+    return g;
+}
+
+// Candidate ranges of (y, z) cell-row combination cc of a row: segment A
+// (cell rank range [a0, a1), x not shifted) and segment B ([b0, b1), x
+// shifted by shb), with the y and z image shifts.  The image of each range is
+// also given as a code dx + 3 dy + 9 dz, digit 0 for none, 1 for -L, 2 for +L:
+// `code` for A, code + codeb for B.  Written with selects rather than
+// branches: every lane of a wavefront runs the same instructions.
+struct Seg {
+    int a0, a1, b0, b1;
+    double shy, shz, shb;
+    int code, codeb;
+};
+
+__device__ __forceinline__ Seg cell_row_segment(const Stencil& st,
+                                                const int32_t* __restrict__ cell_start,
+                                                const RowGeo& g, int cc) {
+    Seg sg;
+    // (y, z) offsets of the combination: the FP32 quotient is within one of
+    // the exact one for any realistic count (< 2^22), and corrected
+    int kz = (int)(((float)cc + 0.5f) * st.inv_kyn);
+    int ky = cc - kz * st.ky_n;
+    kz = ky < 0 ? kz - 1 : (ky >= st.ky_n ? kz + 1 : kz);
+    ky = cc - kz * st.ky_n;
+    int wz = kz, wy = ky;
+    float gz = 0.0f, gy = 0.0f;
+    int code = 0;
+    double shz = 0.0, shy = 0.0;
+    if (!st.fullz) {
+        const int oz = kz - st.Rz;
+        gz = cell_gap(oz, g.fz);
+        wz = g.cz + oz;
+        const bool lo = wz < 0, hi = wz >= st.nz;
+        wz += lo ? st.nz : (hi ? -st.nz : 0);
+        code += lo ? 9 : (hi ? 18 : 0);
+        shz = lo ? -st.box[2] : (hi ? st.box[2] : 0.0);
+    }
+    if (!st.fully) {
+        const int oy = ky - st.Ry;
+        gy = cell_gap(oy, g.fy);
+        wy = g.cy + oy;
+        const bool lo = wy < 0, hi = wy >= st.ny;
+        wy += lo ? st.ny : (hi ? -st.ny : 0);
+        code += lo ? 3 : (hi ? 6 : 0);
+        shy = lo ? -st.box[1] : (hi ? st.box[1] : 0.0);
+    }
+    // squared distance from the atom to this cell row (FP32, conservative)
+    const float d2 = fmaf(gy * gy, st.cs2y, gz * gz * st.cs2z);
+    const bool visit = g.ok && cc < st.ncombo && d2 < st.rsd2f;
+    int xa0 = 0, xa1 = st.nx, xb0 = 0, xb1 = 0, codeb = 0;
+    double shb = 0.0;
+    if (!st.fullx) {
+        // chord half-width in cells, inflated (far above the rounding of the
+        // FP32 quantities it comes from)
+        const float wcell =
+            __builtin_amdgcn_sqrtf(fmaxf(st.rsd2f - d2, 0.0f) * st.inv_cs2x) * 1.00001f + 1e-5f;
+        const int u0 = max(g.cx + (int)floorf(g.fx - wcell), g.cx - st.Rx);
+        const int u1 = min(g.cx + (int)floorf(g.fx + wcell), g.cx + st.Rx);
+        const bool lo = u0 < 0, hi = u1 >= st.nx;
+        // [u0, -1] wraps to the top with -L; [nx, u1] to the bottom with +L
+        xa0 = lo ? 0 : u0;
+        xa1 = hi ? st.nx : u1 + 1;
+        xb0 = lo ? u0 + st.nx : 0;
+        xb1 = lo ? st.nx : (hi ? u1 - st.nx + 1 : 0);
+        codeb = lo ? 1 : (hi ? 2 : 0);
+        shb = lo ? -st.box[0] : (hi ? st.box[0] : 0.0);
+    }
+    // a wavefront past the last combination may hold out-of-grid rows: clamp
+    // the row it would read (its ranges are empty anyway)
+    const int rowbase = visit ? (wz * st.ny + wy) * st.nx : 0;
+    const bool va = visit && xa1 > xa0, vb = visit && xb1 > xb0;
+    // both loads issued together (a row's whole cell range is in the grid)
+    const int a0 = cell_start[rowbase + (va ? xa0 : 0)];
+    const int a1 = cell_start[rowbase + (va ? xa1 : 0)];
+    sg.a0 = a0;
+    sg.a1 = va ? a1 : a0;
+    sg.b0 = 0;
+    sg.b1 = 0;
+    if (vb) {
+        sg.b0 = cell_start[rowbase + xb0];
+        sg.b1 = cell_start[rowbase + xb1];
+    }
+    sg.shy = shy;
+    sg.shz = shz;
+    sg.shb = shb;
+    sg.code = code;
+    sg.codeb = codeb;
+    return sg;
 }
 
 // Value of lane q of each group of GB consecutive lanes, for every lane of the
@@ -124,21 +274,9 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
 
     const double4 qi = a.spos[rank];
     const int32_t self = (int32_t)__double_as_longlong(qi.w);
-    const int nx = sy.nc[0], ny = sy.nc[1], nz = sy.nc[2];
-    // cell of the atom and its fractional position in the cell (FP32, culling only)
-    const int cx = lj_cell_coord(qi.x, sy.inv_cs[0], nx);
-    const int cy = lj_cell_coord(qi.y, sy.inv_cs[1], ny);
-    const int cz = lj_cell_coord(qi.z, sy.inv_cs[2], nz);
-    const float fx = (float)(qi.x * sy.inv_cs[0] - cx);
-    const float fy = (float)(qi.y * sy.inv_cs[1] - cy);
-    const float fz = (float)(qi.z * sy.inv_cs[2] - cz);
-
-    const bool fullx = ANYFULL && sy.full[0], fully = ANYFULL && sy.full[1],
-               fullz = ANYFULL && sy.full[2];
-    const int Rx = sy.reach[0], Ry = fully ? 0 : sy.reach[1], Rz = fullz ? 0 : sy.reach[2];
-    const int ky_n = fully ? ny : 2 * Ry + 1, kz_n = fullz ? nz : 2 * Rz + 1;
-    const float rsd2f = sy.rsd2f;
-    const float inv_cs2x = 1.0f / sy.cs2f[0];
+    const Stencil stn = make_stencil<ANYFULL>(sy);
+    const RowGeo geo = row_geo(stn, qi, row_ok);
+    const bool fullx = stn.fullx, fully = stn.fully, fullz = stn.fullz;
 
     // the ballot bits of this row's GB lanes
     const uint64_t grp = (GB == LJ_WAVE) ? ~0ull : (((1ull << (GB & 63)) - 1ull) << (cb * GB));
@@ -216,88 +354,6 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
         }
     };
 
-    // Candidate ranges of (y, z) cell-row combination cc: segment A (cell
-    // rank range [a0, a1), x not shifted) and segment B ([b0, b1), x shifted
-    // by shb), with the y and z image shifts.
-    struct Seg {
-        int a0, a1, b0, b1;
-        double shy, shz, shb;
-    };
-    auto segment = [&](int cc) {
-        Seg sg = {0, 0, 0, 0, 0.0, 0.0, 0.0};
-        const int kz = cc / ky_n, ky = cc - kz * ky_n;
-        int wz, wy;
-        float gz = 0.0f, gy = 0.0f;
-        if (fullz) {
-            wz = kz;
-        } else {
-            const int oz = kz - Rz;
-            gz = cell_gap(oz, fz);
-            wz = cz + oz;
-            if (wz < 0) {
-                wz += nz;
-                sg.shz = -sy.box[2];
-            } else if (wz >= nz) {
-                wz -= nz;
-                sg.shz = sy.box[2];
-            }
-        }
-        if (fully) {
-            wy = ky;
-        } else {
-            const int oy = ky - Ry;
-            gy = cell_gap(oy, fy);
-            wy = cy + oy;
-            if (wy < 0) {
-                wy += ny;
-                sg.shy = -sy.box[1];
-            } else if (wy >= ny) {
-                wy -= ny;
-                sg.shy = sy.box[1];
-            }
-        }
-        // squared distance from the atom to this cell row (FP32, conservative)
-        const float d2 = fmaf(gy * gy, sy.cs2f[1], gz * gz * sy.cs2f[2]);
-        int xa0 = 0, xa1 = 0, xb0 = 0, xb1 = 0;
-        if (row_ok && cc < ky_n * kz_n && d2 < rsd2f) {
-            if (fullx) {
-                xa1 = nx;
-            } else {
-                // chord half-width in cells, inflated (far above the rounding
-                // of the FP32 quantities it comes from)
-                const float wcell =
-                    __builtin_amdgcn_sqrtf((rsd2f - d2) * inv_cs2x) * 1.00001f + 1e-5f;
-                int u0 = cx + (int)floorf(fx - wcell);
-                int u1 = cx + (int)floorf(fx + wcell);
-                u0 = max(u0, cx - Rx);
-                u1 = min(u1, cx + Rx);
-                if (u0 < 0) {           // [u0, -1] wraps to the top with -L
-                    xb0 = u0 + nx;
-                    xb1 = nx;
-                    sg.shb = -sy.box[0];
-                    xa1 = u1 + 1;
-                } else if (u1 >= nx) {  // [nx, u1] wraps to the bottom with +L
-                    xa0 = u0;
-                    xa1 = nx;
-                    xb1 = u1 - nx + 1;
-                    sg.shb = sy.box[0];
-                } else {
-                    xa0 = u0;
-                    xa1 = u1 + 1;
-                }
-            }
-        }
-        const int rowbase = (wz * ny + wy) * nx;
-        if (xa1 > xa0) {
-            sg.a0 = cell_start[rowbase + xa0];
-            sg.a1 = cell_start[rowbase + xa1];
-        }
-        if (xb1 > xb0) {
-            sg.b0 = cell_start[rowbase + xb0];
-            sg.b1 = cell_start[rowbase + xb1];
-        }
-        return sg;
-    };
     // the row's member q computed combination c0 + q for the whole row
     auto scan_member = [&](const Seg& mine, auto qc) {
         constexpr int Q = decltype(qc)::value;
@@ -312,9 +368,9 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
 
     // The (y, z) cell-row combinations, GB at a time: lane g of a row works
     // out combination c0 + g, then the row scans the GB combinations in order.
-    const int ncombo = ky_n * kz_n;
+    const int ncombo = stn.ncombo;
     for (int c0 = 0; c0 < ncombo; c0 += GB) {
-        const Seg mine = segment(c0 + g);
+        const Seg mine = cell_row_segment(stn, cell_start, geo, c0 + g);
         scan_member(mine, std::integral_constant<int, 0>());
         if constexpr (GB > 1) {
             if (c0 + 1 < ncombo) scan_member(mine, std::integral_constant<int, 1>());
@@ -346,6 +402,327 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
     if ((lane % SL) == 0) {
         a.slice_iters[slice] = iters;
         a.slice_stats[slice] = make_int4(over, tot, ntest, 0);
+    }
+}
+
+// ------------------------------------------------------------ row walk
+// A wavefront builds RW consecutive rows one at a time, all 64 lanes on one
+// row.  The row's candidate ranges (the nonempty segments of its cell rows, in
+// combination order) are laid end to end into one stream of T candidates, and
+// the wavefront walks the stream 64 at a time: lane l of tile t takes stream
+// position 64 t + l.  Only the last tile of a row has idle lanes, where the
+// per-segment walk above idles the lanes of every short segment.
+//
+// Set-up, two rows at once (one per half-wavefront, a cell-row combination
+// per lane): prefix sums of the ranges' counts and lengths give each range its
+// table entry and its start in the stream; each tile records the entry that
+// holds its position 0 and a bit for every range that starts inside it, so a
+// lane finds its range with one masked bit count.  A row with more ranges or
+// tiles than the table holds walks its segments one at a time instead.
+//
+// Entries are appended to a copy of the row in LDS and written out when the
+// row is done, 16 bytes per lane, so that a row costs one or two store
+// instructions rather than one per tile.  Candidate records are read through a
+// buffer resource spanning the system's atoms: an offset outside it reads zeros
+// and cannot fault.
+constexpr int RT_MAXE = 64;   // table entries (nonempty ranges) per row
+constexpr int RT_NT = 16;     // tiles of 64 stream positions per row
+constexpr int RT_RB = 512;    // entries of a row staged in LDS (the rest go straight out)
+
+struct RowTable {
+    int2 ent[2][RT_MAXE];                  // first rank (system-relative) - stream start, image code
+    unsigned long long starts[2][RT_NT];   // bit p - 1: a range starts at tile position p
+    int first[2][RT_NT];                   // entry holding tile position 0
+    double4 shift[27];                     // image shift of each code
+    int4 row[RT_RB / 4];                   // the row being built, entries 0 .. RT_RB - 1
+};
+
+// Inclusive prefix sum within each 32-lane half of the wavefront (all lanes
+// active): shifts within rows of 16 lanes, then row 1 and 3 add the last
+// lane of row 0 and 2.
+__device__ __forceinline__ int half_scan(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, true);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true);   // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    return v;
+}
+
+// Orders the wavefront's LDS accesses before and after this point.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double dword_pair(unsigned int lo, unsigned int hi) {
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+template <int G, bool HALF, bool ANYFULL>
+__global__ __launch_bounds__(LJ_BLOCK, 8) void k_neigh_rows(NeighArgs a) {
+    constexpr int C = LJ_WAVE / G;          // rows per slice of the layout
+    constexpr int RW = C > 8 ? C : 8;       // rows per wavefront: whole slices
+    __shared__ RowTable tables[LJ_WAVES_PER_BLOCK];
+    RowTable& tb = tables[threadIdx.x >> 6];
+    const int lane = threadIdx.x & (LJ_WAVE - 1);
+    const int hw = lane >> 5, hl = lane & 31;
+    const int wv = __builtin_amdgcn_readfirstlane(
+        (int)lj_xcd_block(blockIdx.x, gridDim.x) * LJ_WAVES_PER_BLOCK + (threadIdx.x >> 6));
+    const int64_t row0 = (int64_t)wv * RW;
+    if (row0 >= a.nslices * C) return;   // whole wavefront leaves together
+    const int sid = __builtin_amdgcn_readfirstlane(a.slice_sys[row0 / C]);
+    const lj_sys& sy = a.sys[sid];
+    // the system's constants as values: the list stores in the loops below
+    // would otherwise make the compiler read them again from memory
+    const int S = sy.cap / G;
+    const int cap = sy.cap;
+    const double rs2 = sy.rs2;
+    const int64_t nsys = sy.n;
+    const double hbx = sy.half_box[0], hby = sy.half_box[1], hbz = sy.half_box[2];
+    const int64_t slice_first = row0 / C;
+    const int64_t lr0 = row0 - sy.slice0 * C;   // first row within the system
+    int32_t* __restrict__ wcol =
+        a.col + sy.col0 + (slice_first - sy.slice0) * (int64_t)S * LJ_WAVE;
+    const int32_t* __restrict__ cell_start = a.cell_start + sy.cell0;
+    const int atom0 = (int)sy.atom0;
+    const double4* __restrict__ spos = a.spos + atom0;
+    const uint64_t nbytes = (uint64_t)nsys * 32u;
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)spos, (short)0, (int)(nbytes > 0xffffffffull ? 0xffffffffull : nbytes),
+        0x00020000);
+    const Stencil stn = make_stencil<ANYFULL>(sy);
+
+    if (lane < 27) {
+        const int dx = lane % 3, dy = (lane / 3) % 3, dz = lane / 9;
+        auto img = [](int d, double L) { return d == 1 ? -L : (d == 2 ? L : 0.0); };
+        tb.shift[lane] = make_double4(img(dx, stn.box[0]), img(dy, stn.box[1]),
+                                      img(dz, stn.box[2]), 0.0);
+    }
+
+    // entry k of the row at slot offset `slot`
+    auto put = [&](uint32_t slot, uint32_t k, int32_t v) {
+        wcol[slot + (k / (uint32_t)G) * (uint32_t)LJ_WAVE + (k % (uint32_t)G)] = v;
+    };
+    auto row_slot = [&](int rr) {
+        return (uint32_t)((rr / C) * S * LJ_WAVE + (rr % C) * G);
+    };
+
+    int keep_len = 0, keep_self = 0, keep_atom = 0;   // lane r: row r of the wavefront
+    int sl_mx = 0, sl_over = 0, sl_tot = 0, sl_tests = 0;
+
+    // the atoms of all the wavefront's rows, one load, kept in LDS
+    __shared__ double4 row_q[LJ_WAVES_PER_BLOCK][RW];
+    double4* rq = row_q[threadIdx.x >> 6];
+    if (lane < RW) {
+        const int64_t lr = lr0 + lane;
+        rq[lane] = spos[lr < nsys ? (int)lr : 0];
+    }
+
+    for (int p = 0; p < RW; p += 2) {
+        // ---- set-up: the table of row p + hw
+        wave_lds_sync();
+        const RowGeo geo = row_geo(stn, rq[p + hw], lr0 + p + hw < nsys);
+        if (hl < RT_NT) tb.starts[hw][hl] = 0ull;
+        wave_lds_sync();
+        int ebase = 0, fbase = 0;
+        bool img = false;
+        for (int cb = 0; cb < stn.ncombo; cb += 32) {
+            const Seg sg = cell_row_segment(stn, cell_start, geo, cb + hl);
+            const int mA = sg.a1 - sg.a0, mB = sg.b1 - sg.b0;
+            const int nA = mA > 0 ? 1 : 0, nB = mB > 0 ? 1 : 0;
+            const int ei = half_scan(nA + nB), fi = half_scan(mA + mB);
+            int e = ebase + ei - (nA + nB), f = fbase + fi - (mA + mB);
+            auto add_range = [&](int s0, int m, int code) {
+                if (e < RT_MAXE) tb.ent[hw][e] = make_int2(s0 - atom0 - f, code);
+                const int t0 = f >> 6, p0 = f & 63;
+                if (p0 != 0 && t0 < RT_NT) atomicOr(&tb.starts[hw][t0], 1ull << (p0 - 1));
+                const int t1 = (f + m - 1) >> 6;
+                for (int t = (f + 63) >> 6; t <= t1 && t < RT_NT; ++t) tb.first[hw][t] = e;
+                ++e;
+                f += m;
+            };
+            if (nA) add_range(sg.a0, mA, sg.code);
+            if (nB) add_range(sg.b0, mB, sg.code + sg.codeb);
+            img = img || (nA && sg.code != 0) || nB;
+            ebase += __shfl(ei, (lane & 32) | 31, LJ_WAVE);
+            fbase += __shfl(fi, (lane & 32) | 31, LJ_WAVE);
+        }
+        const uint64_t img_ball = __builtin_amdgcn_ballot_w64(img);
+        wave_lds_sync();
+
+        // ---- walk rows p and p + 1
+#pragma unroll 1
+        for (int h = 0; h < 2; ++h) {
+            const int rr = p + h;
+            const int T = __builtin_amdgcn_readlane(fbase, 32 * h);
+            const int E = __builtin_amdgcn_readlane(ebase, 32 * h);
+            const bool row_img = ((img_ball >> (32 * h)) & 0xffffffffull) != 0;
+            const int64_t lrh = lr0 + rr;
+            const bool okh = lrh < nsys;
+            const int rh = okh ? (int)lrh : 0;
+            const double4 qi = rq[rr];
+            const int32_t self = (int32_t)__double_as_longlong(qi.w);
+            const uint32_t slot = row_slot(rr);
+            int cnt = 0;
+
+            // candidate srel (system-relative rank): its record, then the
+            // test and the append
+            struct Rec {
+                double x, y, z;
+                int32_t j;
+            };
+            auto fetch = [&](int srel) {
+                const uint32_t off = (uint32_t)srel << 5;
+                const auto v0 = __builtin_amdgcn_raw_buffer_load_b128(rsrc, off, 0, 0);
+                const auto v1 = __builtin_amdgcn_raw_buffer_load_b128(rsrc, off + 16u, 0, 0);
+                return Rec{dword_pair(v0[0], v0[1]), dword_pair(v0[2], v0[3]),
+                           dword_pair(v1[0], v1[1]), (int32_t)v1[2]};
+            };
+            auto test_append = [&](const Rec& q, int srel, bool valid, double shx, double shy,
+                                   double shz, auto img_c) {
+                constexpr bool IMG = decltype(img_c)::value;
+                double tx = q.x - qi.x, ty = q.y - qi.y, tz = q.z - qi.z;
+                if (ANYFULL) {
+                    tx = stn.fullx ? nearest(tx, stn.box[0], hbx) : (IMG ? tx + shx : tx);
+                    ty = stn.fully ? nearest(ty, stn.box[1], hby) : (IMG ? ty + shy : ty);
+                    tz = stn.fullz ? nearest(tz, stn.box[2], hbz) : (IMG ? tz + shz : tz);
+                } else if (IMG) {
+                    tx = tx + shx;
+                    ty = ty + shy;
+                    tz = tz + shz;
+                }
+                const double r2 = r2_rounded(tx, ty, tz);
+                bool own = true;
+                if (HALF) own = ((srel > rh) != (((srel + rh) & 1) != 0));
+                const bool pass = valid & (q.j != self) & own & (r2 < rs2);
+                const uint64_t ball = __builtin_amdgcn_ballot_w64(pass);
+                const int k = (int)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(ball >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ball, (uint32_t)cnt));
+                if (pass & (k < cap)) {
+                    if (k < RT_RB)
+                        reinterpret_cast<int*>(tb.row)[k] = q.j;
+                    else
+                        put(slot, (uint32_t)k, q.j);
+                }
+                cnt += (int)__builtin_popcountll(ball);
+            };
+            // table entry of the lane's stream position in tile t
+            auto entry = [&](int t) {
+                const unsigned long long X = tb.starts[h][t];
+                const int k = (int)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(X >> 32),
+                    __builtin_amdgcn_mbcnt_lo((uint32_t)X, (uint32_t)tb.first[h][t]));
+                return tb.ent[h][k];
+            };
+            // software-pipelined: the entry of tile t + 1 is looked up while
+            // the records of tile t are in flight
+            auto walk = [&](auto img_c) {
+                const int nt = (T + 63) >> 6;
+                int2 en = nt > 0 ? entry(0) : make_int2(0, 0);
+                for (int t = 0; t < nt; ++t) {
+                    const int pos = (t << 6) + lane;
+                    const int srel = en.x + pos;
+                    const Rec q = fetch(srel);
+                    double shx = 0.0, shy = 0.0, shz = 0.0;
+                    if constexpr (decltype(img_c)::value) {
+                        const double4 sh = tb.shift[en.y];
+                        shx = sh.x;
+                        shy = sh.y;
+                        shz = sh.z;
+                    }
+                    if (t + 1 < nt) en = entry(t + 1);
+                    test_append(q, srel, pos < T, shx, shy, shz, img_c);
+                }
+            };
+            if (T <= RT_NT * LJ_WAVE && E <= RT_MAXE) {
+                if (row_img)
+                    walk(std::true_type());
+                else
+                    walk(std::false_type());
+            } else {
+                // a long row: its segments one at a time, 64 candidates per pass
+                const RowGeo g1 = row_geo(stn, qi, okh);
+                for (int cc = 0; cc < stn.ncombo; ++cc) {
+                    const Seg sg = cell_row_segment(stn, cell_start, g1, cc);
+                    const int mA = sg.a1 - sg.a0, mB = sg.b1 - sg.b0;
+                    for (int o = 0; o < mA; o += LJ_WAVE) {
+                        const int srel = sg.a0 - atom0 + o + lane;
+                        test_append(fetch(srel), srel, o + lane < mA, 0.0, sg.shy, sg.shz,
+                                    std::true_type());
+                    }
+                    for (int o = 0; o < mB; o += LJ_WAVE) {
+                        const int srel = sg.b0 - atom0 + o + lane;
+                        test_append(fetch(srel), srel, o + lane < mB, sg.shb, sg.shy, sg.shz,
+                                    std::true_type());
+                    }
+                }
+            }
+
+            const int len = cnt < cap ? cnt : cap;
+            // write out the staged entries, SW per lane (runs of G entries are
+            // contiguous in the layout), the last group completed with the
+            // row's own atom
+            {
+                constexpr int SW = G < 4 ? G : 4;
+                wave_lds_sync();
+                const int fl = len <= RT_RB ? (len + SW - 1) / SW * SW : RT_RB;
+                const int* rowb = reinterpret_cast<const int*>(tb.row);
+                for (int k0 = lane * SW; k0 < fl; k0 += LJ_WAVE * SW) {
+                    int32_t* dst = wcol + slot + (uint32_t)(k0 / G) * LJ_WAVE + (uint32_t)(k0 % G);
+                    if constexpr (SW == 4) {
+                        int4 v = tb.row[k0 / 4];
+                        v.x = k0 < len ? v.x : self;
+                        v.y = k0 + 1 < len ? v.y : self;
+                        v.z = k0 + 2 < len ? v.z : self;
+                        v.w = k0 + 3 < len ? v.w : self;
+                        *reinterpret_cast<int4*>(dst) = v;
+                    } else if constexpr (SW == 2) {
+                        int2 v = make_int2(rowb[k0], rowb[k0 + 1]);
+                        v.x = k0 < len ? v.x : self;
+                        v.y = k0 + 1 < len ? v.y : self;
+                        *reinterpret_cast<int2*>(dst) = v;
+                    } else {
+                        *dst = k0 < len ? rowb[k0] : self;
+                    }
+                }
+                wave_lds_sync();
+            }
+            if (lane == rr) {
+                keep_len = len;
+                keep_self = self;
+                keep_atom = okh ? self : 0;
+            }
+            if (cnt > cap && lane == 0) atomicOr(&a.st->flags, LJ_DEV_ROW_OVERFLOW);
+            sl_mx = max(sl_mx, len);
+            sl_over = max(sl_over, cnt);
+            sl_tot += len;
+            sl_tests += T;
+            if ((rr + 1) % C == 0) {
+                // the slice is complete: pad its rows with their own atom
+                const int iters = (sl_mx + G - 1) / G;
+                constexpr int SW = G < 4 ? G : 4;
+                for (int j = rr + 1 - C; j <= rr; ++j) {
+                    const int lj = __builtin_amdgcn_readlane(keep_len, j);
+                    const int sj = __builtin_amdgcn_readlane(keep_self, j);
+                    const uint32_t sl = row_slot(j);
+                    // written so far: the staged entries rounded up to SW
+                    const int from = lj <= RT_RB ? (lj + SW - 1) / SW * SW : lj;
+                    for (int k = from + lane; k < iters * G; k += LJ_WAVE) put(sl, (uint32_t)k, sj);
+                }
+                if (lane == 0) {
+                    const int64_t slice = slice_first + rr / C;
+                    a.slice_iters[slice] = iters;
+                    a.slice_stats[slice] = make_int4(sl_over, sl_tot, sl_tests, 0);
+                }
+                sl_mx = sl_over = sl_tot = sl_tests = 0;
+            }
+        }
+    }
+    if (lane < RW) {
+        a.row_atom[row0 + lane] = keep_atom;
+        a.row_len[row0 + lane] = keep_len;
     }
 }
 
@@ -425,12 +802,37 @@ lj_status launch_g(lj_ctx* ctx, const NeighArgs& a, bool half, bool anyfull) {
     return LJ_OK;
 }
 
+template <int G>
+lj_status launch_rows(lj_ctx* ctx, const NeighArgs& a, bool half, bool anyfull) {
+    constexpr int C = LJ_WAVE / G;
+    constexpr int RW = C > 8 ? C : 8;
+    const int64_t rows = a.nslices * C;
+    const int64_t waves = (rows + RW - 1) / RW;
+    const int64_t blocks = (waves + LJ_WAVES_PER_BLOCK - 1) / LJ_WAVES_PER_BLOCK;
+    dim3 grid((unsigned)blocks), block(LJ_BLOCK);
+    lj_prof_scope prof(ctx, LJ_PROF_NEIGH);
+    if (half) {
+        if (anyfull)
+            hipLaunchKernelGGL((k_neigh_rows<G, true, true>), grid, block, 0, ctx->stream, a);
+        else
+            hipLaunchKernelGGL((k_neigh_rows<G, true, false>), grid, block, 0, ctx->stream, a);
+    } else {
+        if (anyfull)
+            hipLaunchKernelGGL((k_neigh_rows<G, false, true>), grid, block, 0, ctx->stream, a);
+        else
+            hipLaunchKernelGGL((k_neigh_rows<G, false, false>), grid, block, 0, ctx->stream, a);
+    }
+    LJ_HIP(hipGetLastError());
+    return LJ_OK;
+}
+
 }  // namespace
 
 int lj_build_lanes(const lj_ctx* ctx, int lanes) {
-    // tuned value (default 4), at most the layout's lanes per row
+    // tuned value; default: the whole wavefront on one row (any layout).
+    // 1, 2 or 4 lanes per row are at most the layout's lanes per row.
     int gb = ctx->tune[LJ_TUNE_BUILD_LANES];
-    if (gb != 1 && gb != 2 && gb != 4) gb = 4;
+    if (gb != 1 && gb != 2 && gb != 4) return LJ_WAVE;
     return gb > lanes ? lanes : gb;
 }
 
@@ -453,11 +855,14 @@ lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l, bool s
     const int gb = l->build_lanes;
     lj_status st;
 #define LJ_GB(G)                                                              \
-    (gb == 1 ? launch_g<G, 1>(ctx, a, half, anyfull)                          \
+    (gb == LJ_WAVE ? launch_rows<G>(ctx, a, half, anyfull)                    \
+     : gb == 1 ? launch_g<G, 1>(ctx, a, half, anyfull)                        \
              : gb == 2 ? launch_g<G, (G >= 2 ? 2 : 1)>(ctx, a, half, anyfull) \
                        : launch_g<G, (G >= 4 ? 4 : (G >= 2 ? 2 : 1))>(ctx, a, half, anyfull))
     switch (l->lanes) {
-        case 1: st = launch_g<1, 1>(ctx, a, half, anyfull); break;
+        case 1: st = gb == LJ_WAVE ? launch_rows<1>(ctx, a, half, anyfull)
+                           : launch_g<1, 1>(ctx, a, half, anyfull);
+                break;
         case 2: st = LJ_GB(2); break;
         case 4: st = LJ_GB(4); break;
         case 8: st = LJ_GB(8); break;

@@ -133,7 +133,7 @@ def bench_batch512(steps: int = 100, warmup: int = 0, cpu: bool = False):
         pos = torch.from_numpy(synth.aos4(pos0)).to(dev)
         torch.cuda.synchronize()
         tuned = autotune.tune_batch(ctx, pos, n, box, rc, 0.3,
-                                    space={"lanes": (4, 8), "build_lanes": (2, 4),
+                                    space={"lanes": (4, 8), "build_lanes": (64, 4),
                                            "batch": (2, 4), "cell_div": (2,)}, reps=5)
     best = tuned["best"]
     autotune.apply(ctx, best)

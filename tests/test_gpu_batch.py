@@ -52,14 +52,20 @@ def canon(ij):
 
 @pytest.mark.parametrize("kind", [0, 1])
 @pytest.mark.parametrize("layout", [0, 1])
-def test_batch_pairs_and_forces(lj, ctx, oracle, kind, layout):
+@pytest.mark.parametrize("build_lanes", [0, 4])
+def test_batch_pairs_and_forces(lj, ctx, oracle, kind, layout, build_lanes):
     systems = small_batch()
     off = offsets(systems)
     n, box, rc = params(systems)
     pos = concat(systems, layout)
     torch.cuda.synchronize()
+    ctx.tune_set(lj.LJ_TUNE_BUILD_LANES, build_lanes)
+    try:
+        with torch.cuda.stream(ctx.stream):
+            nl = lj.lj_build_neighbors_batch(ctx, pos, n, box, rc, 0.3, kind=kind)
+    finally:
+        ctx.tune_set(lj.LJ_TUNE_BUILD_LANES, 0)
     with torch.cuda.stream(ctx.stream):
-        nl = lj.lj_build_neighbors_batch(ctx, pos, n, box, rc, 0.3, kind=kind)
         ones = np.ones(len(systems))
         F, E, W, C = lj.lj_forces_batch(ctx, pos, nl, ones, ones, rc)
         ctx.sync()

@@ -361,7 +361,7 @@ def test_cells_structure(lj, ctx):
         assert np.all(p >= lo - 1e-12) and np.all(p <= lo + side + 1e-12)
 
 
-@pytest.mark.parametrize("knob,value", [(0, 1), (0, 2), (0, 4), (1, 2), (1, 4), (1, 8),
+@pytest.mark.parametrize("knob,value", [(0, 1), (0, 2), (0, 4), (0, 64), (1, 2), (1, 4), (1, 8),
                                         (2, 1), (2, 2), (2, 3), (2, 4)])
 @pytest.mark.parametrize("kind", [0, 1])
 def test_tuning_knobs_do_not_change_results(lj, ctx, oracle, knob, value, kind):
@@ -383,6 +383,80 @@ def test_tuning_knobs_do_not_change_results(lj, ctx, oracle, knob, value, kind):
             check_forces(s, forces_to_np(F, 0), E.item(), W.item(), n.item(), ref)
         finally:
             ctx.tune_set(knob, 0)
+
+
+# build-lanes knob: 64 = the whole wavefront builds one row at a time (the
+# default), 4 = groups of four lanes build sixteen rows side by side
+@pytest.fixture(params=[64, 4])
+def build_mode(request, lj, ctx):
+    ctx.tune_set(lj.LJ_TUNE_BUILD_LANES, request.param)
+    yield request.param
+    ctx.tune_set(lj.LJ_TUNE_BUILD_LANES, 0)
+
+
+def _pairs_and_forces(lj, ctx, s, ref, kind, lanes=8, layout=0):
+    pos = to_dev(s.pos, layout)
+    nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=kind, lanes=lanes)
+    lj.lj_update_neighbors(ctx, pos, s.box, nl)      # the in-place path too
+    ctx.sync()
+    ij = nl.pairs()
+    sel = ij if kind == 0 else ij[ij[:, 0] < ij[:, 1]]
+    assert np.array_equal(canon(sel), ref[0])
+    d = nl.info()
+    assert d.entries == ij.shape[0] and d.max_row <= d.cap
+    F, E, W, n = lj.lj_forces(ctx, pos, s.box, s.eps, s.sigma, s.rc, nl)
+    torch.cuda.synchronize()
+    check_forces(s, forces_to_np(F, layout), E.item(), W.item(), n.item(), ref)
+    return nl
+
+
+@pytest.mark.parametrize("name", list(SYSTEMS))
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("lanes", [1, 4, 8, 64])
+def test_build_pairs_and_forces(lj, ctx, oracle, build_mode, name, kind, lanes):
+    """Both build modes give the exact pair set at every layout width (the
+    one-row-per-wavefront build: 64, 16, 8 and 8 rows per wavefront)."""
+    s = SYSTEMS[name]()
+    _pairs_and_forces(lj, ctx, s, reference(oracle, s), kind, lanes)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_build_long_rows(lj, ctx, oracle, build_mode, kind):
+    """Rows with more candidate ranges or tiles than the row walk's table (rc =
+    5: about 1,400 candidates per row) take its segment-at-a-time path."""
+    s = synth.small_fcc(10, 1.0, 0.05, 21, rc=5.0)
+    nl = _pairs_and_forces(lj, ctx, s, reference(oracle, s), kind)
+    assert nl.info().tests / s.n > 1024
+
+
+def test_build_dense_cluster(lj, ctx, oracle, build_mode):
+    """A dense cluster in a dilute box: short rows and long rows in one build."""
+    rng = np.random.Generator(np.random.PCG64(10))
+    L = 30.0
+    sites = synth.fcc_sites(4, 4 * 1.2)
+    gas = rng.uniform(0, L, size=(200, 3))
+    gas = gas[np.all(np.abs(gas - 15.0) > 5.0, axis=1)]
+    pos = np.concatenate([sites + 12.0, gas])
+    s = synth.System(pos=pos, box=np.array([L, L, L]), rc=2.5, skin=0.3, name="cluster")
+    for kind in (0, 1):
+        _pairs_and_forces(lj, ctx, s, reference(oracle, s), kind)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_build_lj131k(lj, ctx, oracle, build_mode, kind):
+    s = synth.lj131k()
+    _pairs_and_forces(lj, ctx, s, reference(oracle, s), kind)
+
+
+def test_build_overflow_reported(lj, ctx, build_mode):
+    s = synth.lj4k()
+    nl = lj.lj_build_neighbors(ctx, to_dev(s.pos, 0), s.box, s.rc, s.skin, kind=1)
+    dense = (s.pos * 0.5) + 0.25 * s.box[0]
+    lj.lj_update_neighbors(ctx, to_dev(dense, 0), s.box, nl)
+    with pytest.raises(lj.LJError) as e:
+        ctx.sync()
+    assert e.value.status == lj.LJ_E_CAPACITY
+    ctx.sync()
 
 
 def test_update_neighbors_after_motion(lj, ctx, oracle):
