@@ -149,6 +149,7 @@ void cells_release(lj_cells* c) {
     dfree(c->order_tmp);
     dfree(c->order);
     dfree(c->spos);
+    dfree(c->spos32);
     dfree(c->block_sums);
     delete c;
 }
@@ -221,6 +222,7 @@ lj_status alloc_cells(int nsys, const int64_t* n, const double* box, const doubl
         (st = dmalloc(&c->cell_start, cells + 1)) || (st = dmalloc(&c->cid, atoms)) || (st = dmalloc(&c->slot, atoms)) ||
         (st = dmalloc(&c->order_tmp, atoms)) || (st = dmalloc(&c->order, atoms)) ||
         (st = dmalloc(&c->spos, atoms + LJ_SPOS_PAD)) ||
+        (st = dmalloc(&c->spos32, atoms + LJ_SPOS_PAD)) ||
         (st = dmalloc(&c->block_sums, lj_scan_workspace(cells)))) {
         cells_release(c);
         return st;
@@ -288,6 +290,27 @@ void sys_list(lj_sys& sy, double rc, double skin) {
     // FP32 culling: inflated by a relative 1e-5, far above the FP32 rounding of
     // the cell-relative quantities it is computed from
     sy.rsd2f = (float)(rsd * rsd * (1.0 + 1e-5));
+    // Band of the FP32 pair test.  Coordinates in [0, L) rounded to FP32 are
+    // off by at most u L (u = 2^-24); a difference t of two of them, its
+    // rounding and an FP32 image shift of +-L leave each component of the
+    // separation off by e <= 4 u L + u |t|; then for r <= rx = 1.001 rs
+    //   |r2_fp32 - r^2| <= 2 sqrt(3) r e + 3 e^2 + 3.01 u r^2,
+    // and the FP64 r^2 is within a few 2^-53 (L rx + rx^2) of r^2.  Beyond rx
+    // both tests reject (r^2 - rs^2 > 0.002 rs^2 far exceeds either bound),
+    // so outside twice the bound the FP32 test decides exactly as the FP64
+    // test does.
+    {
+        const double u = 5.9604644775390625e-08, u64 = 1.1102230246251565e-16;
+        const double rx = 1.001 * sy.rs;
+        const double e = 4.0 * u * L + u * rx;
+        const double b32 = 2.0 * 1.7320508075688772 * rx * e + 3.0 * e * e + 3.01 * u * rx * rx;
+        const double b64 = 16.0 * u64 * (L * rx + rx * rx);
+        const double band = 2.0 * (b32 + b64);
+        const float lo = (float)(sy.rs2 - band), hi = (float)(sy.rs2 + band);
+        // round outward
+        sy.r2lo = (double)lo > sy.rs2 - band ? nextafterf(lo, 0.0f) : lo;
+        sy.r2hi = (double)hi < sy.rs2 + band ? nextafterf(hi, 3.0e38f) : hi;
+    }
     for (int d = 0; d < 3; ++d) {
         sy.cs2f[d] = (float)(sy.cs[d] * sy.cs[d]);
         sy.reach[d] = (int)ceil(rsd / sy.cs[d]);

@@ -81,13 +81,14 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_place(int64_t n, const int32_t* __
 
 // One thread per position p of the cell-grouped order: the atom there is
 // ranked among its cell's atoms by index (the number with a smaller index),
-// which puts every cell in index order.  Writes order[] and spos[].
+// which puts every cell in index order.  Writes order[], spos[] and spos32[].
 __global__ __launch_bounds__(LJ_BLOCK) void k_rank(int64_t n, const int32_t* __restrict__ cid,
                                                    const int32_t* __restrict__ cell_start,
                                                    const int32_t* __restrict__ order_tmp,
                                                    const double* __restrict__ pos, int layout,
                                                    int32_t* __restrict__ order,
-                                                   double4* __restrict__ spos) {
+                                                   double4* __restrict__ spos,
+                                                   float4* __restrict__ spos32) {
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int v = order_tmp[p];
@@ -99,6 +100,7 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_rank(int64_t n, const int32_t* __r
     load_xyz(pos, n, layout, v, x, y, z);
     order[s0 + rank] = v;
     spos[s0 + rank] = make_double4(x, y, z, __longlong_as_double((long long)v));
+    spos32[s0 + rank] = make_float4((float)x, (float)y, (float)z, __int_as_float(v));
 }
 
 // ------------------------------------------------------------------ scan
@@ -333,7 +335,8 @@ lj_status lj_launch_cells(lj_ctx* ctx, const double* pos, int layout, lj_cells* 
     LJ_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_rank, dim3(grid_for(c->n, LJ_BLOCK)), dim3(LJ_BLOCK), 0, s, c->n,
                        (const int32_t*)c->cid, (const int32_t*)c->cell_start,
-                       (const int32_t*)c->order_tmp, pos, layout, c->order, c->spos);
+                       (const int32_t*)c->order_tmp, pos, layout, c->order, c->spos,
+                       c->spos32);
     LJ_HIP(hipGetLastError());
     return LJ_OK;
 }

@@ -57,6 +57,9 @@ struct lj_sys {
     double box[3], half_box[3], inv_box[3], inv_cs[3], cs[3];
     float cs2f[3];         // cell side^2 (FP32, culling only)
     float rsd2f;           // (rs + delta)^2, inflated (culling only)
+    float r2lo, r2hi;      // FP32 pair test: r^2 below r2lo is a pair and at or above
+                           // r2hi is not, whatever the FP64 test gives; in between
+                           // the FP64 test decides
     double rs, rc_list, skin, rs2;
     // list
     int64_t slice0, nslices, col0;
@@ -126,6 +129,8 @@ struct lj_cells {
     int32_t* order_tmp;            // n (unsorted within cells)
     int32_t* order;                // n
     double4* spos;                 // n + LJ_SPOS_PAD
+    float4* spos32;                // n + LJ_SPOS_PAD: the same rounded to FP32 (x, y, z,
+                                   // atom index bits)
     int32_t* block_sums;           // scan workspace
     bool counts_dirty;             // count[] may be non-zero (a build was interrupted)
 };

@@ -41,6 +41,7 @@ struct NeighArgs {
     const int32_t* slice_sys;
     const int32_t* cell_start;
     const double4* spos;
+    const float4* spos32;  // the same rounded to FP32 (x, y, z, atom index bits)
     int32_t* row_atom;
     int32_t* row_len;
     int32_t* slice_iters;
@@ -420,6 +421,13 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
 // lane finds its range with one masked bit count.  A row with more ranges or
 // tiles than the table holds walks its segments one at a time instead.
 //
+// Pair test.  Unless a dimension is scanned whole, each candidate is first
+// tested on its 16-byte FP32 record (one load instead of two for the 32-byte
+// FP64 record): r^2 below the system's r2lo is a pair and r^2 at or above
+// r2hi is not, bounds set from the FP32 rounding error (see sys_list) so that
+// these decisions are the FP64 test's; the few candidates in between are
+// tested again in FP64.
+//
 // Entries are appended to a copy of the row in LDS and written out when the
 // row is done, 16 bytes per lane, so that a row costs one or two store
 // instructions rather than one per tile.  Candidate records are read through a
@@ -429,11 +437,16 @@ constexpr int RT_MAXE = 64;   // table entries (nonempty ranges) per row
 constexpr int RT_NT = 16;     // tiles of 64 stream positions per row
 constexpr int RT_RB = 512;    // entries of a row staged in LDS (the rest go straight out)
 
+// Tile map record: bit p - 1 of `starts` is set when a range starts at tile
+// position p; `first` is the entry holding tile position 0.
+struct TileMap {
+    unsigned long long starts;
+    int first, pad;
+};
+
 struct RowTable {
     int2 ent[2][RT_MAXE];                  // first rank (system-relative) - stream start, image code
-    unsigned long long starts[2][RT_NT];   // bit p - 1: a range starts at tile position p
-    int first[2][RT_NT];                   // entry holding tile position 0
-    double4 shift[27];                     // image shift of each code
+    TileMap tile[2][RT_NT];
     int4 row[RT_RB / 4];                   // the row being built, entries 0 .. RT_RB - 1
 };
 
@@ -465,11 +478,27 @@ __global__ __launch_bounds__(LJ_BLOCK, 8) void k_neigh_rows(NeighArgs a) {
     constexpr int C = LJ_WAVE / G;          // rows per slice of the layout
     constexpr int RW = C > 8 ? C : 8;       // rows per wavefront: whole slices
     __shared__ RowTable tables[LJ_WAVES_PER_BLOCK];
+    __shared__ double4 shift[27];     // image shift of each code (the block's system)
+    __shared__ float4 shift32[27];    // the same rounded to FP32
     RowTable& tb = tables[threadIdx.x >> 6];
     const int lane = threadIdx.x & (LJ_WAVE - 1);
     const int hw = lane >> 5, hl = lane & 31;
+    const int64_t blk = lj_xcd_block(blockIdx.x, gridDim.x);
     const int wv = __builtin_amdgcn_readfirstlane(
-        (int)lj_xcd_block(blockIdx.x, gridDim.x) * LJ_WAVES_PER_BLOCK + (threadIdx.x >> 6));
+        (int)blk * LJ_WAVES_PER_BLOCK + (threadIdx.x >> 6));
+    // a block's rows belong to one system (systems own whole 256-row blocks)
+    {
+        const int64_t brow = blk * LJ_WAVES_PER_BLOCK * RW;
+        if (brow < a.nslices * C && threadIdx.x < 27) {
+            const lj_sys& sb = a.sys[a.slice_sys[brow / C]];
+            const int dx = threadIdx.x % 3, dy = (threadIdx.x / 3) % 3, dz = threadIdx.x / 9;
+            auto img = [](int d, double L) { return d == 1 ? -L : (d == 2 ? L : 0.0); };
+            const double sx = img(dx, sb.box[0]), sy_ = img(dy, sb.box[1]), sz = img(dz, sb.box[2]);
+            shift[threadIdx.x] = make_double4(sx, sy_, sz, 0.0);
+            shift32[threadIdx.x] = make_float4((float)sx, (float)sy_, (float)sz, 0.0f);
+        }
+        __syncthreads();
+    }
     const int64_t row0 = (int64_t)wv * RW;
     if (row0 >= a.nslices * C) return;   // whole wavefront leaves together
     const int sid = __builtin_amdgcn_readfirstlane(a.slice_sys[row0 / C]);
@@ -492,14 +521,10 @@ __global__ __launch_bounds__(LJ_BLOCK, 8) void k_neigh_rows(NeighArgs a) {
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
         (void*)spos, (short)0, (int)(nbytes > 0xffffffffull ? 0xffffffffull : nbytes),
         0x00020000);
+    const __amdgpu_buffer_rsrc_t rsrc32 = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)(a.spos32 + atom0), (short)0, (int)(nbytes / 2u), 0x00020000);
+    const float r2lo = sy.r2lo, r2hi = sy.r2hi;
     const Stencil stn = make_stencil<ANYFULL>(sy);
-
-    if (lane < 27) {
-        const int dx = lane % 3, dy = (lane / 3) % 3, dz = lane / 9;
-        auto img = [](int d, double L) { return d == 1 ? -L : (d == 2 ? L : 0.0); };
-        tb.shift[lane] = make_double4(img(dx, stn.box[0]), img(dy, stn.box[1]),
-                                      img(dz, stn.box[2]), 0.0);
-    }
 
     // entry k of the row at slot offset `slot`
     auto put = [&](uint32_t slot, uint32_t k, int32_t v) {
@@ -524,7 +549,7 @@ __global__ __launch_bounds__(LJ_BLOCK, 8) void k_neigh_rows(NeighArgs a) {
         // ---- set-up: the table of row p + hw
         wave_lds_sync();
         const RowGeo geo = row_geo(stn, rq[p + hw], lr0 + p + hw < nsys);
-        if (hl < RT_NT) tb.starts[hw][hl] = 0ull;
+        if (hl < RT_NT) tb.tile[hw][hl].starts = 0ull;
         wave_lds_sync();
         int ebase = 0, fbase = 0;
         bool img = false;
@@ -537,9 +562,9 @@ __global__ __launch_bounds__(LJ_BLOCK, 8) void k_neigh_rows(NeighArgs a) {
             auto add_range = [&](int s0, int m, int code) {
                 if (e < RT_MAXE) tb.ent[hw][e] = make_int2(s0 - atom0 - f, code);
                 const int t0 = f >> 6, p0 = f & 63;
-                if (p0 != 0 && t0 < RT_NT) atomicOr(&tb.starts[hw][t0], 1ull << (p0 - 1));
+                if (p0 != 0 && t0 < RT_NT) atomicOr(&tb.tile[hw][t0].starts, 1ull << (p0 - 1));
                 const int t1 = (f + m - 1) >> 6;
-                for (int t = (f + 63) >> 6; t <= t1 && t < RT_NT; ++t) tb.first[hw][t] = e;
+                for (int t = (f + 63) >> 6; t <= t1 && t < RT_NT; ++t) tb.tile[hw][t].first = e;
                 ++e;
                 f += m;
             };
@@ -610,10 +635,10 @@ __global__ __launch_bounds__(LJ_BLOCK, 8) void k_neigh_rows(NeighArgs a) {
             };
             // table entry of the lane's stream position in tile t
             auto entry = [&](int t) {
-                const unsigned long long X = tb.starts[h][t];
+                const TileMap tm = tb.tile[h][t];
                 const int k = (int)__builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(X >> 32),
-                    __builtin_amdgcn_mbcnt_lo((uint32_t)X, (uint32_t)tb.first[h][t]));
+                    (uint32_t)(tm.starts >> 32),
+                    __builtin_amdgcn_mbcnt_lo((uint32_t)tm.starts, (uint32_t)tm.first));
                 return tb.ent[h][k];
             };
             // software-pipelined: the entry of tile t + 1 is looked up while
@@ -627,7 +652,7 @@ __global__ __launch_bounds__(LJ_BLOCK, 8) void k_neigh_rows(NeighArgs a) {
                     const Rec q = fetch(srel);
                     double shx = 0.0, shy = 0.0, shz = 0.0;
                     if constexpr (decltype(img_c)::value) {
-                        const double4 sh = tb.shift[en.y];
+                        const double4 sh = shift[en.y];
                         shx = sh.x;
                         shy = sh.y;
                         shz = sh.z;
@@ -636,11 +661,87 @@ __global__ __launch_bounds__(LJ_BLOCK, 8) void k_neigh_rows(NeighArgs a) {
                     test_append(q, srel, pos < T, shx, shy, shz, img_c);
                 }
             };
+            // the same with the FP32 test first (no dimension scanned whole);
+            // conditions are kept as 64-bit lane masks
+            const float qxf = (float)qi.x, qyf = (float)qi.y, qzf = (float)qi.z;
+            const int lim = cap < RT_RB ? cap : RT_RB;   // appends that need no check
+            auto walk32 = [&](auto img_c) {
+                constexpr bool IMG = decltype(img_c)::value;
+                const int nt = (T + 63) >> 6;
+                int2 en = nt > 0 ? entry(0) : make_int2(0, 0);
+                for (int t = 0; t < nt; ++t) {
+                    const int pos = (t << 6) + lane;
+                    const int srel = en.x + pos;
+                    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc32, (uint32_t)srel << 4,
+                                                                         0, 0);
+                    const int code = en.y;
+                    if (t + 1 < nt) en = entry(t + 1);
+                    float tx = __uint_as_float(v[0]) - qxf, ty = __uint_as_float(v[1]) - qyf,
+                          tz = __uint_as_float(v[2]) - qzf;
+                    if constexpr (IMG) {
+                        const float4 sh = shift32[code];
+                        tx = tx + sh.x;
+                        ty = ty + sh.y;
+                        tz = tz + sh.z;
+                    }
+                    float r2f;
+                    {
+#pragma clang fp contract(off)
+                        r2f = (tx * tx + ty * ty) + tz * tz;
+                    }
+                    const int rem = T - (t << 6);   // stream positions left, > 0
+                    const uint64_t valid = rem >= LJ_WAVE ? ~0ull : ((1ull << rem) - 1ull);
+                    const uint64_t in = __builtin_amdgcn_ballot_w64(r2f < r2lo) & valid;
+                    const uint64_t amb = __builtin_amdgcn_ballot_w64(r2f < r2hi) & valid & ~in;
+                    uint64_t exact = 0;
+                    if (amb != 0) {
+                        // rare: the FP64 test for the candidates in the band
+                        bool ex = false;
+                        if (__builtin_amdgcn_inverse_ballot_w64(amb)) {
+                            const Rec q = fetch(srel);
+                            double ex_ = q.x - qi.x, ey = q.y - qi.y, ez = q.z - qi.z;
+                            if constexpr (IMG) {
+                                const double4 sh = shift[code];
+                                ex_ = ex_ + sh.x;
+                                ey = ey + sh.y;
+                                ez = ez + sh.z;
+                            }
+                            ex = r2_rounded(ex_, ey, ez) < rs2;
+                        }
+                        exact = __builtin_amdgcn_ballot_w64(ex) & amb;
+                    }
+                    const int32_t j = (int32_t)v[3];
+                    uint64_t pass = (in | exact) & __builtin_amdgcn_ballot_w64(j != self);
+                    if (HALF) pass &= __builtin_amdgcn_ballot_w64((srel > rh) !=
+                                                                  (((srel + rh) & 1) != 0));
+                    const int k = (int)__builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(pass >> 32),
+                        __builtin_amdgcn_mbcnt_lo((uint32_t)pass, (uint32_t)cnt));
+                    const int npass = (int)__builtin_popcountll(pass);
+                    if (cnt + npass <= lim) {
+                        if (__builtin_amdgcn_inverse_ballot_w64(pass))
+                            reinterpret_cast<int*>(tb.row)[k] = j;
+                    } else if (__builtin_amdgcn_inverse_ballot_w64(pass) && k < cap) {
+                        if (k < RT_RB)
+                            reinterpret_cast<int*>(tb.row)[k] = j;
+                        else
+                            put(slot, (uint32_t)k, j);
+                    }
+                    cnt += npass;
+                }
+            };
             if (T <= RT_NT * LJ_WAVE && E <= RT_MAXE) {
-                if (row_img)
-                    walk(std::true_type());
-                else
-                    walk(std::false_type());
+                if (ANYFULL) {
+                    if (row_img)
+                        walk(std::true_type());
+                    else
+                        walk(std::false_type());
+                } else {
+                    if (row_img)
+                        walk32(std::true_type());
+                    else
+                        walk32(std::false_type());
+                }
             } else {
                 // a long row: its segments one at a time, 64 candidates per pass
                 const RowGeo g1 = row_geo(stn, qi, okh);
@@ -843,6 +944,7 @@ lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l, bool s
     a.slice_sys = l->slice_sys;
     a.cell_start = c->cell_start;
     a.spos = c->spos;
+    a.spos32 = c->spos32;
     a.row_atom = l->row_atom;
     a.row_len = l->row_len;
     a.slice_iters = l->slice_iters;
