@@ -106,9 +106,11 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_rank(int64_t n, const int32_t* __r
 // ------------------------------------------------------------------ scan
 // Large arrays, two passes over tiles of SCAN_ITEMS x LJ_BLOCK values: the
 // sum of every tile, then each tile adds up the sums of the tiles before it
-// and scans itself.
-constexpr int SCAN_ITEMS = 16;
-constexpr int SCAN_TILE = SCAN_ITEMS * LJ_BLOCK;   // 4096
+// and scans itself.  Thread t of a tile holds the 4 contiguous values
+// [4 t, 4 t + 4), loaded and stored as one 16-byte vector (the whole tile is
+// one contiguous run per wavefront).
+constexpr int SCAN_ITEMS = 4;
+constexpr int SCAN_TILE = SCAN_ITEMS * LJ_BLOCK;   // 1024
 
 __device__ __forceinline__ int wave_isum(int x) {
 #pragma unroll
@@ -149,18 +151,19 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int* lds, int& total)
     return off + x - v;
 }
 
+// Values [4 i, 4 i + 4) of the array (zeros past its end m).
+__device__ __forceinline__ int4 load4(const int32_t* __restrict__ in, int64_t i4, int64_t m) {
+    const int64_t i = 4 * i4;
+    if (i + 4 <= m) return reinterpret_cast<const int4*>(in)[i4];
+    return make_int4(i < m ? in[i] : 0, i + 1 < m ? in[i + 1] : 0, i + 2 < m ? in[i + 2] : 0, 0);
+}
+
 __global__ __launch_bounds__(LJ_BLOCK) void k_scan_reduce(const int32_t* __restrict__ in,
                                                           int64_t m,
                                                           int32_t* __restrict__ tile_sums) {
     __shared__ int lds[LJ_WAVES_PER_BLOCK];
-    const int64_t base = blockIdx.x * (int64_t)SCAN_TILE;
-    int s = 0;
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        const int64_t idx = base + k * LJ_BLOCK + threadIdx.x;
-        s += idx < m ? in[idx] : 0;
-    }
-    s = block_sum(s, lds);
+    const int4 v = load4(in, blockIdx.x * (int64_t)LJ_BLOCK + threadIdx.x, m);
+    const int s = block_sum(v.x + v.y + v.z + v.w, lds);
     if (threadIdx.x == 0) tile_sums[blockIdx.x] = s;
 }
 
@@ -173,25 +176,24 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_scan_tiles(int32_t* __restrict__ i
     int before = 0;
     for (int t = threadIdx.x; t < (int)blockIdx.x; t += LJ_BLOCK) before += tile_sums[t];
     before = block_sum(before, lds);
-    const int64_t base = blockIdx.x * (int64_t)SCAN_TILE + threadIdx.x * (int64_t)SCAN_ITEMS;
-    int v[SCAN_ITEMS];
-    int s = 0;
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        v[k] = (base + k < m) ? in[base + k] : 0;
-        s += v[k];
-    }
+    const int64_t i4 = blockIdx.x * (int64_t)LJ_BLOCK + threadIdx.x, i = 4 * i4;
+    const int4 v = load4(in, i4, m);
     if (clear_in) {
-#pragma unroll
-        for (int k = 0; k < SCAN_ITEMS; ++k)
-            if (base + k < m) in[base + k] = 0;
+        if (i + 4 <= m) {
+            reinterpret_cast<int4*>(in)[i4] = make_int4(0, 0, 0, 0);
+        } else {
+            for (int64_t k = i; k < m; ++k) in[k] = 0;
+        }
     }
     int total;
-    int run = before + block_exclusive_scan(s, lds, total);
-#pragma unroll
-    for (int k = 0; k < SCAN_ITEMS; ++k) {
-        if (base + k < m) out[base + k] = run;
-        run += v[k];
+    const int run = before + block_exclusive_scan(v.x + v.y + v.z + v.w, lds, total);
+    const int4 o = make_int4(run, run + v.x, run + v.x + v.y, run + v.x + v.y + v.z);
+    if (i + 4 <= m) {
+        reinterpret_cast<int4*>(out)[i4] = o;
+    } else {
+        if (i < m) out[i] = o.x;
+        if (i + 1 < m) out[i + 1] = o.y;
+        if (i + 2 < m) out[i + 2] = o.z;
     }
     if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[m] = before + total;
 }
@@ -288,7 +290,7 @@ lj_status lj_launch_zero(hipStream_t s, void* p, int64_t bytes) {
 lj_status lj_launch_scan(hipStream_t s, int32_t* in, int32_t* out, int64_t m, int32_t* work,
                          bool clear_in) {
     const int64_t nt = (m + SCAN_TILE - 1) / SCAN_TILE;
-    if (nt > SCAN_TILE) return lj_fail(LJ_E_CAPACITY, "scan: more than 16.7M elements");
+    if (nt > 16 * SCAN_TILE) return lj_fail(LJ_E_CAPACITY, "scan: more than 16.7M elements");
     if (m == 0) return lj_launch_zero(s, out, sizeof(int32_t));
     if (m <= SCAN1_MAX) {
         hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SCAN1_THREADS), 0, s, in, out, m,

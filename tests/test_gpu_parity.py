@@ -341,12 +341,14 @@ def test_errors(lj, ctx):
     assert e.value.status == lj.LJ_E_INVALID
 
 
-def test_cells_structure(lj, ctx):
+# 35^3 = 42,875 cells: the multi-tile prefix sum with a ragged last tile
+@pytest.mark.parametrize("min_cell,ncell", [(3.3, 4), (0.45, 35)])
+def test_cells_structure(lj, ctx, min_cell, ncell):
     s = synth.permuted(synth.lj4k(), 5)
     pos = to_dev(s.pos, 0)
-    cells = lj.lj_build_cells(ctx, pos, s.box, 3.3)
+    cells = lj.lj_build_cells(ctx, pos, s.box, min_cell)
     nc, n = cells.info()
-    assert n == s.n and nc == (4, 4, 4)
+    assert n == s.n and nc == (ncell, ncell, ncell)
     cs, order = cells.export()
     assert cs[0] == 0 and cs[-1] == s.n and np.all(np.diff(cs) >= 0)
     assert np.array_equal(np.sort(order), np.arange(s.n))
