@@ -421,12 +421,12 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
 // lane finds its range with one masked bit count.  A row with more ranges or
 // tiles than the table holds walks its segments one at a time instead.
 //
-// Pair test.  Unless a dimension is scanned whole, each candidate is first
-// tested on its 16-byte FP32 record (one load instead of two for the 32-byte
-// FP64 record): r^2 below the system's r2lo is a pair and r^2 at or above
-// r2hi is not, bounds set from the FP32 rounding error (see sys_list) so that
-// these decisions are the FP64 test's; the few candidates in between are
-// tested again in FP64.
+// Pair test.  Unless one of its system's dimensions is scanned whole, each
+// candidate is first tested on its 16-byte FP32 record (one load instead of
+// two for the 32-byte FP64 record): r^2 below the system's r2lo is a pair and
+// r^2 at or above r2hi is not, bounds set from the FP32 rounding error (see
+// sys_list) so that these decisions are the FP64 test's; the few candidates
+// in between are tested again in FP64.
 //
 // Entries are appended to a copy of the row in LDS and written out when the
 // row is done, 16 bytes per lane, so that a row costs one or two store
@@ -469,12 +469,19 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Mask of the lanes below `rem` (none for rem <= 0, all for rem >= 64).
+__device__ __forceinline__ uint64_t lanes_below(int rem) {
+    return rem >= LJ_WAVE ? ~0ull : (rem <= 0 ? 0ull : ((1ull << rem) - 1ull));
+}
+
 __device__ __forceinline__ double dword_pair(unsigned int lo, unsigned int hi) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// At least 7 wavefronts per SIMD (up to 72 VGPRs): at 8 (64 VGPRs) the set-up
+// spills to scratch, which costs more than the eighth wavefront gains.
 template <int G, bool HALF, bool ANYFULL>
-__global__ __launch_bounds__(LJ_BLOCK, 8) void k_neigh_rows(NeighArgs a) {
+__global__ __launch_bounds__(LJ_BLOCK, 7) void k_neigh_rows(NeighArgs a) {
     constexpr int C = LJ_WAVE / G;          // rows per slice of the layout
     constexpr int RW = C > 8 ? C : 8;       // rows per wavefront: whole slices
     __shared__ RowTable tables[LJ_WAVES_PER_BLOCK];
@@ -605,7 +612,24 @@ __global__ __launch_bounds__(LJ_BLOCK, 8) void k_neigh_rows(NeighArgs a) {
                 return Rec{dword_pair(v0[0], v0[1]), dword_pair(v0[2], v0[3]),
                            dword_pair(v1[0], v1[1]), (int32_t)v1[2]};
             };
-            auto test_append = [&](const Rec& q, int srel, bool valid, double shx, double shy,
+            // the lanes of `pass` append their candidate j in lane order
+            const int lim = cap < RT_RB ? cap : RT_RB;   // appends that need no check
+            auto append = [&](uint64_t pass, int32_t j) {
+                const int k = (int)__builtin_amdgcn_mbcnt_hi(
+                    (uint32_t)(pass >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)pass, (uint32_t)cnt));
+                const int npass = (int)__builtin_popcountll(pass);
+                if (cnt + npass <= lim) {
+                    if (__builtin_amdgcn_inverse_ballot_w64(pass))
+                        reinterpret_cast<int*>(tb.row)[k] = j;
+                } else if (__builtin_amdgcn_inverse_ballot_w64(pass) && k < cap) {
+                    if (k < RT_RB)
+                        reinterpret_cast<int*>(tb.row)[k] = j;
+                    else
+                        put(slot, (uint32_t)k, j);
+                }
+                cnt += npass;
+            };
+            auto test_append = [&](const Rec& q, int srel, uint64_t valid, double shx, double shy,
                                    double shz, auto img_c) {
                 constexpr bool IMG = decltype(img_c)::value;
                 double tx = q.x - qi.x, ty = q.y - qi.y, tz = q.z - qi.z;
@@ -619,19 +643,11 @@ __global__ __launch_bounds__(LJ_BLOCK, 8) void k_neigh_rows(NeighArgs a) {
                     tz = tz + shz;
                 }
                 const double r2 = r2_rounded(tx, ty, tz);
-                bool own = true;
-                if (HALF) own = ((srel > rh) != (((srel + rh) & 1) != 0));
-                const bool pass = valid & (q.j != self) & own & (r2 < rs2);
-                const uint64_t ball = __builtin_amdgcn_ballot_w64(pass);
-                const int k = (int)__builtin_amdgcn_mbcnt_hi(
-                    (uint32_t)(ball >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ball, (uint32_t)cnt));
-                if (pass & (k < cap)) {
-                    if (k < RT_RB)
-                        reinterpret_cast<int*>(tb.row)[k] = q.j;
-                    else
-                        put(slot, (uint32_t)k, q.j);
-                }
-                cnt += (int)__builtin_popcountll(ball);
+                uint64_t pass = __builtin_amdgcn_ballot_w64(r2 < rs2) & valid &
+                                __builtin_amdgcn_ballot_w64(q.j != self);
+                if (HALF) pass &= __builtin_amdgcn_ballot_w64((srel > rh) !=
+                                                              (((srel + rh) & 1) != 0));
+                append(pass, q.j);
             };
             // table entry of the lane's stream position in tile t
             auto entry = [&](int t) {
@@ -658,13 +674,12 @@ __global__ __launch_bounds__(LJ_BLOCK, 8) void k_neigh_rows(NeighArgs a) {
                         shz = sh.z;
                     }
                     if (t + 1 < nt) en = entry(t + 1);
-                    test_append(q, srel, pos < T, shx, shy, shz, img_c);
+                    test_append(q, srel, lanes_below(T - (t << 6)), shx, shy, shz, img_c);
                 }
             };
             // the same with the FP32 test first (no dimension scanned whole);
             // conditions are kept as 64-bit lane masks
             const float qxf = (float)qi.x, qyf = (float)qi.y, qzf = (float)qi.z;
-            const int lim = cap < RT_RB ? cap : RT_RB;   // appends that need no check
             auto walk32 = [&](auto img_c) {
                 constexpr bool IMG = decltype(img_c)::value;
                 const int nt = (T + 63) >> 6;
@@ -689,8 +704,7 @@ __global__ __launch_bounds__(LJ_BLOCK, 8) void k_neigh_rows(NeighArgs a) {
 #pragma clang fp contract(off)
                         r2f = (tx * tx + ty * ty) + tz * tz;
                     }
-                    const int rem = T - (t << 6);   // stream positions left, > 0
-                    const uint64_t valid = rem >= LJ_WAVE ? ~0ull : ((1ull << rem) - 1ull);
+                    const uint64_t valid = lanes_below(T - (t << 6));
                     const uint64_t in = __builtin_amdgcn_ballot_w64(r2f < r2lo) & valid;
                     const uint64_t amb = __builtin_amdgcn_ballot_w64(r2f < r2hi) & valid & ~in;
                     uint64_t exact = 0;
@@ -714,24 +728,11 @@ __global__ __launch_bounds__(LJ_BLOCK, 8) void k_neigh_rows(NeighArgs a) {
                     uint64_t pass = (in | exact) & __builtin_amdgcn_ballot_w64(j != self);
                     if (HALF) pass &= __builtin_amdgcn_ballot_w64((srel > rh) !=
                                                                   (((srel + rh) & 1) != 0));
-                    const int k = (int)__builtin_amdgcn_mbcnt_hi(
-                        (uint32_t)(pass >> 32),
-                        __builtin_amdgcn_mbcnt_lo((uint32_t)pass, (uint32_t)cnt));
-                    const int npass = (int)__builtin_popcountll(pass);
-                    if (cnt + npass <= lim) {
-                        if (__builtin_amdgcn_inverse_ballot_w64(pass))
-                            reinterpret_cast<int*>(tb.row)[k] = j;
-                    } else if (__builtin_amdgcn_inverse_ballot_w64(pass) && k < cap) {
-                        if (k < RT_RB)
-                            reinterpret_cast<int*>(tb.row)[k] = j;
-                        else
-                            put(slot, (uint32_t)k, j);
-                    }
-                    cnt += npass;
+                    append(pass, j);
                 }
             };
             if (T <= RT_NT * LJ_WAVE && E <= RT_MAXE) {
-                if (ANYFULL) {
+                if (ANYFULL && (stn.fullx || stn.fully || stn.fullz)) {
                     if (row_img)
                         walk(std::true_type());
                     else
@@ -750,12 +751,12 @@ __global__ __launch_bounds__(LJ_BLOCK, 8) void k_neigh_rows(NeighArgs a) {
                     const int mA = sg.a1 - sg.a0, mB = sg.b1 - sg.b0;
                     for (int o = 0; o < mA; o += LJ_WAVE) {
                         const int srel = sg.a0 - atom0 + o + lane;
-                        test_append(fetch(srel), srel, o + lane < mA, 0.0, sg.shy, sg.shz,
+                        test_append(fetch(srel), srel, lanes_below(mA - o), 0.0, sg.shy, sg.shz,
                                     std::true_type());
                     }
                     for (int o = 0; o < mB; o += LJ_WAVE) {
                         const int srel = sg.b0 - atom0 + o + lane;
-                        test_append(fetch(srel), srel, o + lane < mB, sg.shb, sg.shy, sg.shz,
+                        test_append(fetch(srel), srel, lanes_below(mB - o), sg.shb, sg.shy, sg.shz,
                                     std::true_type());
                     }
                 }
