@@ -544,18 +544,23 @@ __global__ __launch_bounds__(LJ_BLOCK, 7) void k_neigh_rows(NeighArgs a) {
     int keep_len = 0, keep_self = 0, keep_atom = 0;   // lane r: row r of the wavefront
     int sl_mx = 0, sl_over = 0, sl_tot = 0, sl_tests = 0;
 
-    // the atoms of all the wavefront's rows, one load, kept in LDS
+    // the atoms of all the wavefront's rows (one load) and their cell
+    // geometry, one lane per row, kept in LDS
     __shared__ double4 row_q[LJ_WAVES_PER_BLOCK][RW];
+    __shared__ RowGeo row_g[LJ_WAVES_PER_BLOCK][RW];
     double4* rq = row_q[threadIdx.x >> 6];
+    RowGeo* rg = row_g[threadIdx.x >> 6];
     if (lane < RW) {
         const int64_t lr = lr0 + lane;
-        rq[lane] = spos[lr < nsys ? (int)lr : 0];
+        const double4 q = spos[lr < nsys ? (int)lr : 0];
+        rq[lane] = q;
+        rg[lane] = row_geo(stn, q, lr < nsys);
     }
 
     for (int p = 0; p < RW; p += 2) {
         // ---- set-up: the table of row p + hw
         wave_lds_sync();
-        const RowGeo geo = row_geo(stn, rq[p + hw], lr0 + p + hw < nsys);
+        const RowGeo geo = rg[p + hw];
         if (hl < RT_NT) tb.tile[hw][hl].starts = 0ull;
         wave_lds_sync();
         int ebase = 0, fbase = 0;
@@ -745,7 +750,7 @@ __global__ __launch_bounds__(LJ_BLOCK, 7) void k_neigh_rows(NeighArgs a) {
                 }
             } else {
                 // a long row: its segments one at a time, 64 candidates per pass
-                const RowGeo g1 = row_geo(stn, qi, okh);
+                const RowGeo g1 = rg[rr];
                 for (int cc = 0; cc < stn.ncombo; ++cc) {
                     const Seg sg = cell_row_segment(stn, cell_start, g1, cc);
                     const int mA = sg.a1 - sg.a0, mB = sg.b1 - sg.b0;
