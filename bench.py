@@ -6,7 +6,8 @@ HBM: validate and bin the positions into cells, sort them by cell, rebuild
 the Verlet list in place, then compute forces, potential energy and virial
 (lj_update_neighbors + lj_forces).  The workload is the 131,072-atom FCC
 fluid at rho = 1.0, rc = 3.0, skin = 0.3 (32^3 unit cells, jitter +-0.1),
-FP64, positions as padded double4 records in lattice order.
+FP64, positions as padded double4 records, atoms cell-sorted (cubic cells of
+side >= rc + skin, z-major; `--order lattice | permuted` for the others).
 
 Prints ONE JSON line.  `value` = interacting pairs (r < rc, each unordered
 pair once) per second of whole steps.  Extra keys: per-kernel times from HIP
@@ -76,6 +77,16 @@ def measured_traffic(path: str):
         return None
 
 
+def ordered(s, order: str):
+    """The system with its atoms cell-sorted, in lattice order or permuted."""
+    from paper_1806_05713_amd import synth
+    if order == "cellsorted":
+        return synth.cell_sorted(s)
+    if order == "permuted":
+        return synth.permuted(s, synth.SEEDS["perm"])
+    return s
+
+
 def time_steps(torch, fn, steps: int, warmup: int):
     for _ in range(warmup):
         fn()
@@ -122,6 +133,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--kind", choices=["full", "half"], default="full")
+    ap.add_argument("--order", choices=["cellsorted", "lattice", "permuted"],
+                    default="cellsorted", help="atom order of the input")
     ap.add_argument("--lanes", type=int, default=0, help="lanes per list row (0: default)")
     ap.add_argument("--build-lanes", type=int, default=0,
                     help="lanes per row in the list build, 64, 1, 2 or 4 (0: default, 64)")
@@ -174,7 +187,7 @@ def main():
     if args.force_batch:
         ctx.tune_set(lj.LJ_TUNE_FORCE_BATCH, args.force_batch)
 
-    s = synth.lj131k()
+    s = ordered(synth.lj131k(), args.order)
     kind = lj.LJ_LIST_FULL if args.kind == "full" else lj.LJ_LIST_HALF
     pos = torch.from_numpy(synth.aos4(s.pos)).to(dev)
     nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=kind, lanes=args.lanes)
@@ -208,7 +221,8 @@ def main():
 
     force_us = per["force"]
     neigh_us = per["neigh"]
-    default_shape = (args.lanes in (0, 8) and args.build_lanes in (0, 64) and
+    default_shape = (args.order == "cellsorted" and args.lanes in (0, 8) and
+                     args.build_lanes in (0, 64) and
                      args.force_batch in (0, 4))
     bytes_force = algorithmic_force_bytes(s.n, desc.entries)
     force_gbs = bytes_force / (force_us * 1e-6) / 1e9
@@ -237,8 +251,8 @@ def main():
 
     variants = {}
     if not args.no_variants:
-        for order in ("lattice", "permuted"):
-            sv = s if order == "lattice" else synth.permuted(s, synth.SEEDS["perm"])
+        for order in ("cellsorted", "lattice", "permuted"):
+            sv = ordered(synth.lj131k(), order)
             for layout_name, layout in (("aos4", 0), ("soa", 1)):
                 p = torch.from_numpy(synth.aos4(sv.pos) if layout == 0 else synth.soa(sv.pos)).to(dev)
                 f = torch.empty_like(p)
@@ -268,10 +282,13 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "FP64 LJ fluid, 131,072 atoms (32^3 FCC x4), rho=1.0, jitter "
-                               "+-0.1 sigma, eps=sigma=1, rc=3.0, skin=0.3; step = cell "
-                               "binning + list rebuild + forces/energy/virial",
+                               "+-0.1 sigma, eps=sigma=1, rc=3.0, skin=0.3, atoms "
+                               + {"cellsorted": "cell-sorted (cells of side >= rc + skin)",
+                                  "lattice": "in lattice order",
+                                  "permuted": "in random order"}[args.order]
+                               + "; step = cell binning + list rebuild + forces/energy/virial",
                    "atoms": s.n, "list": args.kind, "lanes": desc.lanes, "layout": "aos4",
-                   "order": "lattice", "precision": "fp64",
+                   "order": args.order, "precision": "fp64",
                    "list_entries": desc.entries, "candidate_tests": int(desc.tests),
                    "interacting_pairs": npairs},
         "kernel_us": {k: round(v, 3) for k, v in per.items()},

@@ -106,6 +106,20 @@ def permuted(sys: System, seed: int) -> System:
                                name=sys.name + "-perm")
 
 
+def cell_sorted(sys: System) -> System:
+    """The same system with its atoms sorted by cell: cubic cells of side at
+    least rs = rc + skin (the linked-list cells of the cell method), cells in
+    z-major order (x fastest), atoms of a cell in their previous order."""
+    rs = sys.rc + sys.skin
+    nc = np.maximum(np.floor(sys.box / rs).astype(np.int64), 1)
+    c = np.minimum((sys.pos / (sys.box / nc)).astype(np.int64), nc - 1)
+    cid = (c[:, 2] * nc[1] + c[:, 1]) * nc[0] + c[:, 0]
+    perm = np.lexsort((np.arange(sys.n), cid))
+    vel = None if sys.vel is None else sys.vel[perm].copy()
+    return dataclasses.replace(sys, pos=sys.pos[perm].copy(), vel=vel,
+                               name=sys.name + "-cellsorted")
+
+
 def fcc_system(n: int, rho: float, delta: float, seed: int, rc: float, skin: float,
                T: Optional[float] = None, name: str = "") -> System:
     L = fcc_box(n, rho)

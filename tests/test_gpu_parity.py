@@ -183,8 +183,10 @@ def test_lj131k_fp64(lj, ctx, oracle, kind, layout):
     check_forces(s, forces_to_np(F, layout), E.item(), W.item(), n.item(), ref)
 
 
-def test_lj131k_permuted(lj, ctx, oracle):
-    s = synth.permuted(synth.lj131k(), 77)
+@pytest.mark.parametrize("order", ["permuted", "cellsorted"])
+def test_lj131k_orders(lj, ctx, oracle, order):
+    s = synth.lj131k()
+    s = synth.permuted(s, 77) if order == "permuted" else synth.cell_sorted(s)
     ref = reference(oracle, s)
     pos = to_dev(s.pos, 0)
     for kind in (0, 1):
