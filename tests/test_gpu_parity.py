@@ -550,6 +550,44 @@ def test_cutoffs_are_strict_on_exact_distances(lj, ctx, oracle):
         check_forces(s, forces_to_np(F, 0), E.item(), W.item(), n.item(), ref)
 
 
+def test_pairs_around_rs_in_the_fp32_band(lj, ctx, oracle):
+    """125 isolated pairs at distances spread over the band where the build's
+    FP32 test defers to FP64 (r within ~1e-5 relative of rs) and just outside
+    it, some across periodic faces: the pair set is the oracle's exactly."""
+    rc, skin = 3.0, 0.3
+    rs = rc + skin
+    L = 40.0
+    rng = np.random.Generator(np.random.PCG64(2024))
+    k = 5
+    site = L / k                                   # sites farther apart than 2 rs
+    rel = np.concatenate([np.linspace(-3e-5, 3e-5, 121), [0.0, 1e-16, -1e-16, 2e-16]])
+    pts = []
+    for n, (ix, iy, iz) in enumerate(np.ndindex(k, k, k)):
+        a = (np.array([ix, iy, iz]) + rng.uniform(0.3, 0.7, 3)) * site
+        if n % 7 == 0:
+            a[n % 3] = L - 0.5                     # the partner across the face
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        r = rs * (1.0 + rel[n])
+        if rel[n] == 1e-16:
+            r = np.nextafter(rs, 0.0)
+        elif rel[n] == -1e-16:
+            r = np.nextafter(rs, 10.0)
+        elif rel[n] == 2e-16:
+            r = rs
+        pts += [a, a + r * u]
+    s = synth.System(pos=synth.wrap(np.array(pts), L), box=np.array([L, L, L]), rc=rc,
+                     skin=skin, name="band")
+    ref = reference(oracle, s)
+    assert 0 < ref[0].shape[0] < 125            # some pairs in, some out
+    pos = to_dev(s.pos, 0)
+    for kind in (0, 1):
+        nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=kind)
+        ij = nl.pairs()
+        sel = ij if kind == 0 else ij[ij[:, 0] < ij[:, 1]]
+        assert np.array_equal(canon(sel), ref[0])
+
+
 def test_atom_count_limit(lj, ctx):
     """More than LJ_MAX_ATOMS atoms is refused before any device memory is
     touched (kernels address records with 32-bit byte offsets)."""
