@@ -2,15 +2,19 @@
 // search length rs = rc + skin, found through the cells; Sec. III.C: grouped
 // by i so each row is that atom's SortedList).
 //
-// Work mapping.  Rows are the atoms in cell order.  A wavefront builds
-// 64 / GB consecutive rows with GB lanes per row (GB <= G, the lanes per row
-// of the list layout), and appends straight into the wavefront-sliced slots of
-// the layout: a single pass, no count-then-fill.  With one lane per row
-// (GB = 1) each lane walks its own candidate range with NB candidate records
-// in flight at once (the range may be overrun by up to NB - 1 records, which
-// the cell-sorted position array is padded for; those lanes are masked); with
-// GB > 1 the lanes of a row test consecutive candidates and append in order
-// with a ballot.
+// Work mapping.  Rows are the atoms in cell order, and every entry goes
+// straight into the wavefront-sliced slots of the layout: a single pass, no
+// count-then-fill.  Two kernels, chosen by the build-lanes knob:
+//   k_neigh_rows (the default): a wavefront builds its rows one at a time,
+//     all 64 lanes walking the row's candidates laid end to end (described
+//     where it is defined);
+//   k_neigh: a wavefront builds 64 / GB consecutive rows side by side with
+//     GB lanes per row (GB <= G, the lanes per row of the layout).  With one
+//     lane per row (GB = 1) each lane walks its own candidate range with NB
+//     candidate records in flight at once (the range may be overrun by up to
+//     NB - 1 records, which the cell-sorted position array is padded for;
+//     those lanes are masked); with GB > 1 the lanes of a row test
+//     consecutive candidates and append in order with a ballot.
 //
 // Candidate cells.  Cells have side >= rs/2 by default, so a neighbor lies
 // within R = 2 cells per dimension.  Each row visits only the (y, z) cell rows
@@ -24,6 +28,8 @@
 // Exactness of the pair test.  t = q_j - q_i is formed in FP64 and brought to
 // the nearest image, and r^2 = (tx*tx + ty*ty) + tz*tz with every operation
 // rounded on its own (no FMA contraction); the pair is kept iff r^2 < rs^2.
+// (k_neigh_rows decides most candidates with an FP32 test whose outcome is
+// provably this one, and the rest with this test.)
 // When a dimension has at least 2R + 2 cells the image is known from the cell
 // offset and applied as one addition of -L, 0 or +L, which rounds exactly as
 // the compare-and-subtract form does, because a pair reached through another
