@@ -59,6 +59,22 @@ def apply(ctx: "lj.Context", cfg: dict) -> None:
     ctx.tune_set(lj.LJ_TUNE_CELL_DIV, cfg.get("cell_div", 0))
 
 
+# An NVE step of the library's integrator rebuilds the list every
+# NVE_REBUILD_EVERY steps (its default cadence).
+NVE_REBUILD_EVERY = 10
+
+
+def timings(per: dict) -> dict:
+    """Objectives from per-phase device times (us): build_us (cells + list),
+    force_us, step_us (one rebuild and one force evaluation) and nve_us (an
+    integrator step: the force evaluation plus the rebuild's share)."""
+    build = per["cells"] + per["neigh"]
+    force = per["force"] + per["other"]
+    return {"build_us": build, "force_us": per["force"],
+            "step_us": build + force,
+            "nve_us": force + build / NVE_REBUILD_EVERY}
+
+
 def measure(ctx, pos, box, rc, skin, kind, precision, cfg, reps: int = 20) -> dict:
     """Device time (us) of one list rebuild and one force evaluation with cfg."""
     import torch
@@ -77,8 +93,7 @@ def measure(ctx, pos, box, rc, skin, kind, precision, cfg, reps: int = 20) -> di
     ctx.sync()
     nl.free()
     per = {k: v[0] * 1e3 / max(v[1], 1) for k, v in prof.items()}
-    return {"build_us": per["cells"] + per["neigh"], "force_us": per["force"],
-            "step_us": per["cells"] + per["neigh"] + per["force"] + per["other"]}
+    return timings(per)
 
 
 def tune(ctx, pos, box, rc, skin, kind=lj.LJ_LIST_FULL, precision=lj.LJ_FP64,
@@ -120,8 +135,7 @@ def measure_batch(ctx, pos, n, box, rc, skin, kind, precision, cfg, reps: int = 
     ctx.sync()
     nl.free()
     per = {k: v[0] * 1e3 / max(v[1], 1) for k, v in prof.items()}
-    return {"build_us": per["cells"] + per["neigh"], "force_us": per["force"],
-            "step_us": per["cells"] + per["neigh"] + per["force"] + per["other"]}
+    return timings(per)
 
 
 def tune_batch(ctx, pos, n, box, rc, skin, kind=lj.LJ_LIST_FULL, precision=lj.LJ_FP64,

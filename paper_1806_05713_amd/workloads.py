@@ -132,7 +132,8 @@ def bench_batch512(steps: int = 100, warmup: int = 0, cpu: bool = False):
     with torch.cuda.stream(ctx.stream):
         pos = torch.from_numpy(synth.aos4(pos0)).to(dev)
         torch.cuda.synchronize()
-        tuned = autotune.tune_batch(ctx, pos, n, box, rc, 0.3,
+        # objective: an NVE step (forces every step, a rebuild every 10)
+        tuned = autotune.tune_batch(ctx, pos, n, box, rc, 0.3, objective="nve_us",
                                     space={"lanes": (4, 8), "build_lanes": (64, 4),
                                            "batch": (2, 4), "cell_div": (2,)}, reps=5)
     best = tuned["best"]
