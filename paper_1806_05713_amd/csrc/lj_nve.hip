@@ -9,8 +9,10 @@
 //   k_kick  : v += F dt/2; per-block partial sums of v^2/2 and max |disp|^2
 //   k_log   : one block per system sums its partials in a fixed order and
 //             writes the system's log row (PE, KE, W, max displacement, pairs)
-// The per-atom kernels run over the list's rows (256-row blocks, each inside
-// one system), so every block knows its system and box.  Every product and
+// The per-atom kernels take one thread per row of the list (256-row blocks,
+// each inside one system), so every block knows its system and box, but the
+// thread of a system's k-th row handles the system's k-th atom in memory
+// order, not the row's atom: the arrays stream instead of being gathered.  Every product and
 // sum is rounded on its own, as in the oracle's integrator.  These kernels
 // stream about 100 bytes per atom per step (HBM bound).
 #include <math.h>
@@ -39,9 +41,37 @@ struct lj_nve {
 
 namespace {
 
+// Three components of one atom's record; w is AoS4's fourth double, kept as read.
+struct Rec {
+    double v[3];
+    double w;
+};
+
 template <int LAYOUT>
-__device__ __forceinline__ double* comp(double* a, int64_t n, int64_t i, int d) {
-    return LAYOUT == LJ_AOS4 ? a + 4 * i + d : a + (int64_t)d * n + i;
+__device__ __forceinline__ Rec load_rec(const double* a, int64_t n, int64_t i) {
+    Rec o;
+    if constexpr (LAYOUT == LJ_AOS4) {
+        const double4 q = reinterpret_cast<const double4*>(a)[i];
+        o.v[0] = q.x;
+        o.v[1] = q.y;
+        o.v[2] = q.z;
+        o.w = q.w;
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) o.v[d] = a[(int64_t)d * n + i];
+        o.w = 0.0;
+    }
+    return o;
+}
+
+template <int LAYOUT>
+__device__ __forceinline__ void store_rec(double* a, int64_t n, int64_t i, const Rec& o) {
+    if constexpr (LAYOUT == LJ_AOS4) {
+        reinterpret_cast<double4*>(a)[i] = make_double4(o.v[0], o.v[1], o.v[2], o.w);
+    } else {
+#pragma unroll
+        for (int d = 0; d < 3; ++d) a[(int64_t)d * n + i] = o.v[d];
+    }
 }
 
 struct RowArgs {
@@ -52,12 +82,13 @@ struct RowArgs {
     int64_t n;             // atoms over all systems (SoA stride)
     const lj_sys* sys;
     const int32_t* slice_sys;
-    const int32_t* row_atom;
     int C;                 // rows per slice
     double* partials;
     int64_t* dstep;
 };
 
+// Thread r of the list's row space handles atom atom0 + (r - first row of
+// its system): the system's atoms in memory order, so every array streams.
 template <int LAYOUT>
 __global__ __launch_bounds__(LJ_BLOCK) void k_drift(RowArgs a, double hdt, double dt, int reset,
                                                     int bump_step) {
@@ -67,23 +98,26 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_drift(RowArgs a, double hdt, doubl
         a.slice_sys[(blockIdx.x * (int64_t)LJ_BLOCK) / a.C]);
     const lj_sys& sy = a.sys[sid];
     if (bump_step && blockIdx.x == 0 && threadIdx.x == 0) *a.dstep += 1;
-    if (r - sy.slice0 * a.C >= sy.n) return;
-    const int64_t i = a.row_atom[r];
+    const int64_t t = r - sy.slice0 * a.C;
+    if (t >= sy.n) return;
+    const int64_t i = sy.atom0 + t;
+    Rec v = load_rec<LAYOUT>(a.vel, a.n, i);
+    Rec x = load_rec<LAYOUT>(a.pos, a.n, i);
+    const Rec f = load_rec<LAYOUT>(a.force, a.n, i);
+    double* u = a.disp + 3 * i;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        double* pv = comp<LAYOUT>(a.vel, a.n, i, d);
-        double* px = comp<LAYOUT>(a.pos, a.n, i, d);
-        const double f = *comp<LAYOUT>(const_cast<double*>(a.force), a.n, i, d);
         const double L = sy.box[d];
-        const double v = *pv + hdt * f;
-        const double dx = dt * v;
-        double x = *px + dx;
-        x = x - L * floor(x / L);
-        if (x >= L) x = 0.0;
-        *pv = v;
-        *px = x;
-        a.disp[3 * i + d] = reset ? 0.0 : a.disp[3 * i + d] + dx;
+        v.v[d] = v.v[d] + hdt * f.v[d];
+        const double dx = dt * v.v[d];
+        double xd = x.v[d] + dx;
+        xd = xd - L * floor(xd / L);
+        if (xd >= L) xd = 0.0;
+        x.v[d] = xd;
+        u[d] = reset ? 0.0 : u[d] + dx;
     }
+    store_rec<LAYOUT>(a.vel, a.n, i, v);
+    store_rec<LAYOUT>(a.pos, a.n, i, x);
 }
 
 template <int LAYOUT>
@@ -95,16 +129,15 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_kick(RowArgs a, double hdt) {
         a.slice_sys[(blockIdx.x * (int64_t)LJ_BLOCK) / a.C]);
     const lj_sys& sy = a.sys[sid];
     double ke = 0.0, d2 = 0.0;
-    if (r - sy.slice0 * a.C < sy.n) {
-        const int64_t i = a.row_atom[r];
-        double v[3];
+    const int64_t t = r - sy.slice0 * a.C;
+    if (t < sy.n) {
+        const int64_t i = sy.atom0 + t;
+        Rec v = load_rec<LAYOUT>(a.vel, a.n, i);
+        const Rec f = load_rec<LAYOUT>(a.force, a.n, i);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            double* pv = comp<LAYOUT>(a.vel, a.n, i, d);
-            v[d] = *pv + hdt * *comp<LAYOUT>(const_cast<double*>(a.force), a.n, i, d);
-            *pv = v[d];
-        }
-        ke = 0.5 * ((v[0] * v[0] + v[1] * v[1]) + v[2] * v[2]);
+        for (int d = 0; d < 3; ++d) v.v[d] = v.v[d] + hdt * f.v[d];
+        store_rec<LAYOUT>(a.vel, a.n, i, v);
+        ke = 0.5 * ((v.v[0] * v.v[0] + v.v[1] * v.v[1]) + v.v[2] * v.v[2]);
         const double* u = a.disp + 3 * i;
         d2 = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
     }
@@ -185,7 +218,6 @@ RowArgs row_args(lj_nve* s) {
     a.n = s->list->n;
     a.sys = s->list->dsys;
     a.slice_sys = s->list->slice_sys;
-    a.row_atom = s->list->row_atom;
     a.C = LJ_WAVE / s->list->lanes;
     a.partials = s->partials;
     a.dstep = s->dstep;
