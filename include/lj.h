@@ -314,8 +314,9 @@ LJ_API lj_status lj_tune_get(const lj_ctx* ctx, int32_t knob, int32_t* value);
 #define LJ_PROF_CELLS 0   /* binning, prefix sum, scatter, per-cell sort */
 #define LJ_PROF_NEIGH 1   /* the list-build kernel */
 #define LJ_PROF_FORCE 2   /* the force kernel */
-#define LJ_PROF_OTHER 3   /* zero fills */
-#define LJ_PROF_N 4
+#define LJ_PROF_OTHER 3   /* energy/virial reduction, half-list force write-out, zero fills */
+#define LJ_PROF_INTEGRATE 4  /* NVE: drift, kick (fused or alone), log row */
+#define LJ_PROF_N 5
 /* Start recording (drops anything recorded before). */
 LJ_API lj_status lj_profile_begin(lj_ctx* ctx);
 /* Stop recording, wait for the stream and return, per phase, the summed

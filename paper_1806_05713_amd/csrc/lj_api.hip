@@ -444,7 +444,7 @@ lj_status build_list(lj_ctx* ctx, const double* pos, int32_t layout, int nsys, c
         return st;
     }
     // the force kernel's block partials must fit in the context
-    const int64_t blocks = lj_force_blocks(l->nslices);
+    const int64_t blocks = lj_force_partials(l);
     if (blocks > ctx->partials_cap) {
         double* p = nullptr;
         if ((st = dmalloc(&p, 4 * blocks))) {

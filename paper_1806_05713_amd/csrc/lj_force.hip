@@ -18,9 +18,12 @@
 //            E = 4 eps (A - B) - count V(rc) and W = sum fs r^2 = 24 eps (2A - B)
 // The row's force is summed over its G lanes with cross-lane shuffles.
 // Energy, virial and the pair count are summed per block in a fixed order,
-// and a one-block kernel sums the block partials in a fixed order and writes
+// and one block per system sums the block partials in a fixed order (in two
+// levels when a system has more than 4096 blocks) and writes
 // E = scale * (sum - count * V(rc)), W = scale * sum, count * scale, with
 // scale = 1/2 for a full list (every pair is visited twice).
+#include <algorithm>
+
 #include "lj_internal.h"
 
 namespace {
@@ -136,27 +139,19 @@ __device__ void block_partials(const ForceArgs& a, int64_t blk, double e, double
     }
 }
 
-// One block per system: thread t sums the system's block partials t, t + 1024,
-// ... then a fixed tree; writes the system's energy, virial and pair count.
-__global__ __launch_bounds__(1024) void k_force_reduce(const double* __restrict__ partials,
-                                                       const lj_sys* sys, const lj_fconst* fc,
-                                                       double scale, double* energy,
-                                                       double* virial, int64_t* npairs) {
+// Fixed-order block sum of partial records [b0, b1): thread t adds records
+// t, t + 1024, ... (four loads in flight per pass), then the waves' sums are
+// added in wave order.  The result is valid in thread 0.
+__device__ double3 span_sum(const double4* __restrict__ p, int64_t b0, int64_t b1) {
     __shared__ double red[16][3];
-    const lj_sys& sy = sys[blockIdx.x];
-    const int64_t b0 = sy.slice0 / LJ_WAVES_PER_BLOCK;
-    const int64_t b1 = (sy.slice0 + sy.nslices) / LJ_WAVES_PER_BLOCK;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double se = 0.0, sw = 0.0, sc = 0.0;
-    // four blocks per thread and pass, loaded before they are added (the
-    // order of the sums is fixed by the thread and the pass)
     for (int64_t bb = b0 + threadIdx.x; bb < b1; bb += 4 * 1024) {
         double4 v[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int64_t b = bb + u * 1024;
-            v[u] = b < b1 ? reinterpret_cast<const double4*>(partials)[b]
-                          : make_double4(0.0, 0.0, 0.0, 0.0);
+            v[u] = b < b1 ? p[b] : make_double4(0.0, 0.0, 0.0, 0.0);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -174,16 +169,53 @@ __global__ __launch_bounds__(1024) void k_force_reduce(const double* __restrict_
         red[wave][2] = sc;
     }
     __syncthreads();
+    double3 t = make_double3(0.0, 0.0, 0.0);
     if (threadIdx.x == 0) {
-        double te = 0.0, tw = 0.0, tc = 0.0;
         for (int k = 0; k < 16; ++k) {
-            te += red[k][0];
-            tw += red[k][1];
-            tc += red[k][2];
+            t.x += red[k][0];
+            t.y += red[k][1];
+            t.z += red[k][2];
         }
-        energy[blockIdx.x] = scale * (te - tc * fc[blockIdx.x].vc);
-        virial[blockIdx.x] = scale * tw;
-        if (npairs) npairs[blockIdx.x] = (int64_t)(scale * tc + 0.5);
+    }
+    return t;
+}
+
+// First level for systems with many blocks: block (s, k), k < split, sums
+// the k-th of split equal contiguous spans of system s's block partials.
+__global__ __launch_bounds__(1024) void k_force_reduce_split(const double4* __restrict__ partials,
+                                                             const lj_sys* sys, int split,
+                                                             double4* __restrict__ out) {
+    const int s = blockIdx.x / split, k = blockIdx.x % split;
+    const lj_sys& sy = sys[s];
+    const int64_t b0 = sy.slice0 / LJ_WAVES_PER_BLOCK;
+    const int64_t b1 = (sy.slice0 + sy.nslices) / LJ_WAVES_PER_BLOCK;
+    const int64_t span = (b1 - b0 + split - 1) / split;
+    const int64_t lo = b0 + k * span < b1 ? b0 + k * span : b1;
+    const int64_t hi = lo + span < b1 ? lo + span : b1;
+    const double3 t = span_sum(partials, lo, hi);
+    if (threadIdx.x == 0) out[blockIdx.x] = make_double4(t.x, t.y, t.z, 0.0);
+}
+
+// One block per system: the fixed-order sum of its block partials (split = 1)
+// or of its split first-level sums; writes the system's energy, virial and
+// pair count.
+__global__ __launch_bounds__(1024) void k_force_reduce(const double4* __restrict__ partials,
+                                                       const lj_sys* sys, int split,
+                                                       const lj_fconst* fc, double scale,
+                                                       double* energy, double* virial,
+                                                       int64_t* npairs) {
+    const int s = blockIdx.x;
+    const lj_sys& sy = sys[s];
+    int64_t b0 = (int64_t)s * split, b1 = b0 + split;
+    if (split == 1) {
+        b0 = sy.slice0 / LJ_WAVES_PER_BLOCK;
+        b1 = (sy.slice0 + sy.nslices) / LJ_WAVES_PER_BLOCK;
+    }
+    const double3 t = span_sum(partials, b0, b1);
+    if (threadIdx.x == 0) {
+        energy[s] = scale * (t.x - t.z * fc[s].vc);
+        virial[s] = scale * t.y;
+        if (npairs) npairs[s] = (int64_t)(scale * t.z + 0.5);
     }
 }
 
@@ -364,6 +396,22 @@ int64_t lj_force_blocks(int64_t nslices) {
     return (nslices + LJ_WAVES_PER_BLOCK - 1) / LJ_WAVES_PER_BLOCK;
 }
 
+// One 1024-thread block reads at most this many block partials of a system
+// per reduction level: a single block streams only about 0.1 TB/s, so a
+// 4M-atom system's 125k partials take two levels.
+static const int64_t kReduceSpan = 4096;
+
+int lj_force_split(const lj_list* l) {
+    int64_t most = 0;
+    for (const lj_sys& sy : l->hsys) most = std::max(most, sy.nslices / LJ_WAVES_PER_BLOCK);
+    return (int)std::max<int64_t>(1, (most + kReduceSpan - 1) / kReduceSpan);
+}
+
+int64_t lj_force_partials(const lj_list* l) {
+    const int split = lj_force_split(l);
+    return lj_force_blocks(l->nslices) + (split > 1 ? (int64_t)l->nsys * split : 0);
+}
+
 lj_fconst lj_make_fconst(double eps, double sigma, double rc) {
     lj_fconst f;
     f.rc2 = rc * rc;
@@ -385,7 +433,8 @@ lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int preci
                            const lj_list* l, const lj_fconst* fc, double* force, double* energy,
                            double* virial, int64_t* npairs) {
     const int64_t blocks = lj_force_blocks(l->nslices);
-    if (blocks > ctx->partials_cap) return lj_fail(LJ_E_INVALID, "context partials too small");
+    if (lj_force_partials(l) > ctx->partials_cap)
+        return lj_fail(LJ_E_INVALID, "context partials too small");
     const bool half = l->kind == LJ_LIST_HALF;
     if (half && !l->acc) return lj_fail(LJ_E_INVALID, "half list without its force accumulator");
     ForceArgs a;
@@ -436,9 +485,18 @@ lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int preci
                                l->n, force);
         LJ_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL(k_force_reduce, dim3((unsigned)l->nsys), dim3(1024), 0, ctx->stream,
-                       (const double*)ctx->partials, (const lj_sys*)l->dsys, fc,
-                       half ? 1.0 : 0.5, energy, virial, npairs);
+    const int split = lj_force_split(l);
+    const double4* first = reinterpret_cast<const double4*>(ctx->partials);
+    if (split > 1) {
+        double4* second = reinterpret_cast<double4*>(ctx->partials) + blocks;
+        hipLaunchKernelGGL(k_force_reduce_split, dim3((unsigned)(l->nsys * split)), dim3(1024), 0,
+                           ctx->stream, first, (const lj_sys*)l->dsys, split, second);
+        LJ_HIP(hipGetLastError());
+        first = second;
+    }
+    hipLaunchKernelGGL(k_force_reduce, dim3((unsigned)l->nsys), dim3(1024), 0, ctx->stream, first,
+                       (const lj_sys*)l->dsys, split, fc, half ? 1.0 : 0.5, energy, virial,
+                       npairs);
     LJ_HIP(hipGetLastError());
     return LJ_OK;
 }

@@ -183,6 +183,11 @@ lj_status lj_launch_list_stats(hipStream_t s, lj_list* l);
 int lj_build_lanes(const lj_ctx* ctx, int lanes);
 // forces (lj_force.hip): per-system energy, virial, pair count
 int64_t lj_force_blocks(int64_t nslices);
+// Reduction levels of the force kernel's block partials: the number of
+// first-level spans per system (1: a single level), and the partial records
+// (double4) the context must hold for list l.
+int lj_force_split(const lj_list* l);
+int64_t lj_force_partials(const lj_list* l);
 lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int precision,
                            const lj_list* l, const lj_fconst* fc, double* force, double* energy,
                            double* virial, int64_t* npairs);

@@ -2,20 +2,29 @@
 // batch of independent systems (a single system is a batch of one).
 //
 // Per step (unit mass):
-//   k_drift : v += F dt/2; dx = v dt; x += dx, wrapped into [0, L);
+//   drift   : v += F dt/2; dx = v dt; x += dx, wrapped into [0, L);
 //             disp += dx, or disp = 0 at a rebuild step
 //   [rebuild: cells + list in place]
 //   forces  : F, per-system potential energy, virial, pair count
-//   k_kick  : v += F dt/2; per-block partial sums of v^2/2 and max |disp|^2
+//   kick    : v += F dt/2; per-block partial sums of v^2/2 and max |disp|^2
 //   k_log   : one block per system sums its partials in a fixed order and
 //             writes the system's log row (PE, KE, W, max displacement, pairs)
+// Within a run of consecutive steps the kick that ends step k and the drift
+// that opens step k + 1 use the same force, so one kernel (k_kick_drift) does
+// both and streams each atom once; the velocity between the two half kicks
+// is rounded to FP64 as if it had been stored, so the trajectory is the same
+// bit for bit however a run is cut into launches.  Only a run's last step
+// ends with a kick of its own (k_kick).
 // The per-atom kernels take one thread per row of the list (256-row blocks,
 // each inside one system), so every block knows its system and box, but the
 // thread of a system's k-th row handles the system's k-th atom in memory
-// order, not the row's atom: the arrays stream instead of being gathered.  Every product and
-// sum is rounded on its own, as in the oracle's integrator.  These kernels
-// stream about 100 bytes per atom per step (HBM bound).
+// order, not the row's atom: the arrays stream instead of being gathered.
+// Every product and sum is rounded on its own, as in the oracle's
+// integrator.  Bytes per atom and step (AoS4): drift or kick alone 208 and
+// 120, the fused kernel 232.
 #include <math.h>
+
+#include <algorithm>
 
 #include "lj_internal.h"
 
@@ -87,23 +96,12 @@ struct RowArgs {
     int64_t* dstep;
 };
 
-// Thread r of the list's row space handles atom atom0 + (r - first row of
-// its system): the system's atoms in memory order, so every array streams.
+// Half kick, drift and displacement update of one atom (record index i).
 template <int LAYOUT>
-__global__ __launch_bounds__(LJ_BLOCK) void k_drift(RowArgs a, double hdt, double dt, int reset,
-                                                    int bump_step) {
+__device__ __forceinline__ void drift_atom(const RowArgs& a, const lj_sys& sy, int64_t i, Rec& v,
+                                           const Rec& f, double hdt, double dt, int reset) {
 #pragma clang fp contract(off)
-    const int64_t r = blockIdx.x * (int64_t)LJ_BLOCK + threadIdx.x;
-    const int sid = __builtin_amdgcn_readfirstlane(
-        a.slice_sys[(blockIdx.x * (int64_t)LJ_BLOCK) / a.C]);
-    const lj_sys& sy = a.sys[sid];
-    if (bump_step && blockIdx.x == 0 && threadIdx.x == 0) *a.dstep += 1;
-    const int64_t t = r - sy.slice0 * a.C;
-    if (t >= sy.n) return;
-    const int64_t i = sy.atom0 + t;
-    Rec v = load_rec<LAYOUT>(a.vel, a.n, i);
     Rec x = load_rec<LAYOUT>(a.pos, a.n, i);
-    const Rec f = load_rec<LAYOUT>(a.force, a.n, i);
     double* u = a.disp + 3 * i;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -120,27 +118,20 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_drift(RowArgs a, double hdt, doubl
     store_rec<LAYOUT>(a.pos, a.n, i, x);
 }
 
-template <int LAYOUT>
-__global__ __launch_bounds__(LJ_BLOCK) void k_kick(RowArgs a, double hdt) {
+// Half kick of one atom; returns its kinetic energy and |disp|^2.
+__device__ __forceinline__ void kick_atom(const RowArgs& a, int64_t i, Rec& v, const Rec& f,
+                                          double hdt, double& ke, double& d2) {
 #pragma clang fp contract(off)
-    __shared__ double red[LJ_WAVES_PER_BLOCK][2];
-    const int64_t r = blockIdx.x * (int64_t)LJ_BLOCK + threadIdx.x;
-    const int sid = __builtin_amdgcn_readfirstlane(
-        a.slice_sys[(blockIdx.x * (int64_t)LJ_BLOCK) / a.C]);
-    const lj_sys& sy = a.sys[sid];
-    double ke = 0.0, d2 = 0.0;
-    const int64_t t = r - sy.slice0 * a.C;
-    if (t < sy.n) {
-        const int64_t i = sy.atom0 + t;
-        Rec v = load_rec<LAYOUT>(a.vel, a.n, i);
-        const Rec f = load_rec<LAYOUT>(a.force, a.n, i);
 #pragma unroll
-        for (int d = 0; d < 3; ++d) v.v[d] = v.v[d] + hdt * f.v[d];
-        store_rec<LAYOUT>(a.vel, a.n, i, v);
-        ke = 0.5 * ((v.v[0] * v.v[0] + v.v[1] * v.v[1]) + v.v[2] * v.v[2]);
-        const double* u = a.disp + 3 * i;
-        d2 = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
-    }
+    for (int d = 0; d < 3; ++d) v.v[d] = v.v[d] + hdt * f.v[d];
+    ke = 0.5 * ((v.v[0] * v.v[0] + v.v[1] * v.v[1]) + v.v[2] * v.v[2]);
+    const double* u = a.disp + 3 * i;
+    d2 = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+}
+
+// Block partials of the kinetic energy (fixed-order sum) and of max |disp|^2.
+__device__ __forceinline__ void block_partials(const RowArgs& a, double ke, double d2) {
+    __shared__ double red[LJ_WAVES_PER_BLOCK][2];
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
         ke += __shfl_xor(ke, d, LJ_WAVE);
@@ -163,12 +154,72 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_kick(RowArgs a, double hdt) {
     }
 }
 
+// Thread r of the list's row space handles atom atom0 + (r - first row of
+// its system): the system's atoms in memory order, so every array streams.
+// A negative result means the thread has no atom.
+__device__ __forceinline__ int64_t row_to_atom(const RowArgs& a, const lj_sys*& sy) {
+    const int64_t r = blockIdx.x * (int64_t)LJ_BLOCK + threadIdx.x;
+    const int sid = __builtin_amdgcn_readfirstlane(
+        a.slice_sys[(blockIdx.x * (int64_t)LJ_BLOCK) / a.C]);
+    sy = a.sys + sid;
+    const int64_t t = r - sy->slice0 * a.C;
+    return t < sy->n ? sy->atom0 + t : -1;
+}
+
+// Opens a step: half kick with the current force, drift; bumps the step counter.
+template <int LAYOUT>
+__global__ __launch_bounds__(LJ_BLOCK) void k_drift(RowArgs a, double hdt, double dt, int reset) {
+    const lj_sys* sy;
+    const int64_t i = row_to_atom(a, sy);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.dstep += 1;
+    if (i < 0) return;
+    Rec v = load_rec<LAYOUT>(a.vel, a.n, i);
+    const Rec f = load_rec<LAYOUT>(a.force, a.n, i);
+    drift_atom<LAYOUT>(a, *sy, i, v, f, hdt, dt, reset);
+}
+
+// Ends a step: half kick with the new force; kinetic energy and displacement
+// partials for the step's log row.
+template <int LAYOUT>
+__global__ __launch_bounds__(LJ_BLOCK) void k_kick(RowArgs a, double hdt) {
+    const lj_sys* sy;
+    const int64_t i = row_to_atom(a, sy);
+    double ke = 0.0, d2 = 0.0;
+    if (i >= 0) {
+        Rec v = load_rec<LAYOUT>(a.vel, a.n, i);
+        const Rec f = load_rec<LAYOUT>(a.force, a.n, i);
+        kick_atom(a, i, v, f, hdt, ke, d2);
+        store_rec<LAYOUT>(a.vel, a.n, i, v);
+    }
+    block_partials(a, ke, d2);
+}
+
+// Ends step k and opens step k + 1: the kick's partials are those of step k
+// (its displacement is read before the drift updates it).
+template <int LAYOUT>
+__global__ __launch_bounds__(LJ_BLOCK) void k_kick_drift(RowArgs a, double hdt, double dt,
+                                                         int reset) {
+    const lj_sys* sy;
+    const int64_t i = row_to_atom(a, sy);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *a.dstep += 1;
+    double ke = 0.0, d2 = 0.0;
+    if (i >= 0) {
+        Rec v = load_rec<LAYOUT>(a.vel, a.n, i);
+        const Rec f = load_rec<LAYOUT>(a.force, a.n, i);
+        kick_atom(a, i, v, f, hdt, ke, d2);
+        drift_atom<LAYOUT>(a, *sy, i, v, f, hdt, dt, reset);
+    }
+    block_partials(a, ke, d2);
+}
+
 // One block per system: fixed-order sums of its row blocks' partials, then
-// the system's log row for the current step (row = *dstep).
+// the system's log row for step *dstep + back (back = -1 after the fused
+// kernel has opened the next step).
 __global__ __launch_bounds__(1024) void k_log(const double* __restrict__ partials,
                                               const lj_sys* sys, int C, const double* pe_w,
                                               const int64_t* npairs, const int64_t* dstep,
-                                              double* log, int64_t log_rows, int nsys) {
+                                              int back, double* log, int64_t log_rows,
+                                              int nsys) {
     __shared__ double red[16][2];
     const int s = blockIdx.x;
     const lj_sys& sy = sys[s];
@@ -195,7 +246,7 @@ __global__ __launch_bounds__(1024) void k_log(const double* __restrict__ partial
             k += red[w][0];
             m = fmax(m, red[w][1]);
         }
-        const int64_t row = *dstep;
+        const int64_t row = *dstep + back;
         if (row >= 0 && row < log_rows) {
             double* out = log + 5 * (row * nsys + s);
             out[0] = pe_w[s];
@@ -229,39 +280,63 @@ lj_status forces(lj_nve* s) {
                             s->pe_w, s->pe_w + s->nsys, s->npairs);
 }
 
-lj_status log_row(lj_nve* s) {
+lj_status log_row(lj_nve* s, int back) {
+    lj_prof_scope prof(s->ctx, LJ_PROF_INTEGRATE);
     hipLaunchKernelGGL(k_log, dim3((unsigned)s->nsys), dim3(1024), 0, s->ctx->stream,
                        (const double*)s->partials, (const lj_sys*)s->list->dsys,
                        LJ_WAVE / s->list->lanes, (const double*)s->pe_w,
-                       (const int64_t*)s->npairs, (const int64_t*)s->dstep, s->log, s->log_rows,
-                       s->nsys);
+                       (const int64_t*)s->npairs, (const int64_t*)s->dstep, back, s->log,
+                       s->log_rows, s->nsys);
     LJ_HIP(hipGetLastError());
     return LJ_OK;
 }
 
+// Steps first + 1 .. first + count as one chain: drift, then per step
+// [rebuild] and forces, with the kick that ends a step fused into the drift
+// that opens the next; the chain ends with a kick of its own.  Every step's
+// log row is written before the next step's forces replace its energies.
 template <int LAYOUT>
-lj_status enqueue_step(lj_nve* s, bool rebuild) {
+lj_status enqueue_chain(lj_nve* s, int64_t first, int64_t count) {
     lj_ctx* ctx = s->ctx;
     const dim3 grid((unsigned)s->rblocks), block(LJ_BLOCK);
     const RowArgs a = row_args(s);
-    hipLaunchKernelGGL(k_drift<LAYOUT>, grid, block, 0, ctx->stream, a, 0.5 * s->dt, s->dt,
-                       rebuild ? 1 : 0, 1);
-    LJ_HIP(hipGetLastError());
+    const double hdt = 0.5 * s->dt, dt = s->dt;
     lj_status st;
-    if (rebuild) {
-        lj_list* l = s->list;
-        if ((st = lj_launch_cells(ctx, s->pos, s->layout, l->cells))) return st;
-        if ((st = lj_launch_neighbors(ctx, l->cells, l, false))) return st;
+    for (int64_t k = 1; k <= count; ++k) {
+        const bool rebuild = (first + k) % s->rebuild_every == 0;
+        if (k == 1) {
+            lj_prof_scope prof(ctx, LJ_PROF_INTEGRATE);
+            hipLaunchKernelGGL(k_drift<LAYOUT>, grid, block, 0, ctx->stream, a, hdt, dt,
+                               rebuild ? 1 : 0);
+            LJ_HIP(hipGetLastError());
+        } else {
+            {
+                lj_prof_scope prof(ctx, LJ_PROF_INTEGRATE);
+                hipLaunchKernelGGL(k_kick_drift<LAYOUT>, grid, block, 0, ctx->stream, a, hdt, dt,
+                                   rebuild ? 1 : 0);
+                LJ_HIP(hipGetLastError());
+            }
+            if ((st = log_row(s, -1))) return st;
+        }
+        if (rebuild) {
+            lj_list* l = s->list;
+            if ((st = lj_launch_cells(ctx, s->pos, s->layout, l->cells))) return st;
+            if ((st = lj_launch_neighbors(ctx, l->cells, l, false))) return st;
+        }
+        if ((st = forces(s))) return st;
     }
-    if ((st = forces(s))) return st;
-    hipLaunchKernelGGL(k_kick<LAYOUT>, grid, block, 0, ctx->stream, row_args(s), 0.5 * s->dt);
-    LJ_HIP(hipGetLastError());
-    return log_row(s);
+    {
+        lj_prof_scope prof(ctx, LJ_PROF_INTEGRATE);
+        hipLaunchKernelGGL(k_kick<LAYOUT>, grid, block, 0, ctx->stream, a, hdt);
+        LJ_HIP(hipGetLastError());
+    }
+    return log_row(s, 0);
 }
 
-lj_status step(lj_nve* s, bool rebuild) {
-    return s->layout == LJ_AOS4 ? enqueue_step<LJ_AOS4>(s, rebuild)
-                                : enqueue_step<LJ_SOA>(s, rebuild);
+lj_status chain(lj_nve* s, int64_t first, int64_t count) {
+    if (count <= 0) return LJ_OK;
+    return s->layout == LJ_AOS4 ? enqueue_chain<LJ_AOS4>(s, first, count)
+                                : enqueue_chain<LJ_SOA>(s, first, count);
 }
 
 void release(lj_nve* s) {
@@ -297,7 +372,7 @@ lj_status capture_cycle(lj_nve* s) {
     if (e != hipSuccess) {
         st = lj_hip_fail(e, "hipStreamBeginCapture");
     } else {
-        for (int k = 1; k <= s->rebuild_every && !st; ++k) st = step(s, k == s->rebuild_every);
+        st = chain(s, 0, s->rebuild_every);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(s->cap_stream, &g);
         if (!st && e != hipSuccess) st = lj_hip_fail(e, "hipStreamEndCapture");
@@ -368,7 +443,7 @@ lj_status lj_nve_start(lj_nve* s) {
     else
         hipLaunchKernelGGL(k_kick<LJ_SOA>, grid, block, 0, ctx->stream, row_args(s), 0.0);
     LJ_HIP(hipGetLastError());
-    if ((st = log_row(s))) return st;
+    if ((st = log_row(s, 0))) return st;
     s->steps = 0;
     return LJ_OK;
 }
@@ -386,10 +461,12 @@ lj_status lj_nve_advance(lj_nve* s, int32_t nsteps, int32_t use_graph) {
             left -= k;
             continue;
         }
-        const int64_t next = s->steps + 1;
-        if ((st = step(s, next % k == 0))) return st;
-        s->steps = next;
-        --left;
+        // eagerly: with graphs, up to the next cycle boundary; without, all of it
+        int64_t count = left;
+        if (use_graph) count = std::min(left, k - s->steps % k);
+        if ((st = chain(s, s->steps, count))) return st;
+        s->steps += count;
+        left -= count;
     }
     return LJ_OK;
 }

@@ -38,8 +38,9 @@ EXPORTS = ["lj_create", "lj_destroy", "lj_set_stream", "lj_sync", "lj_build_cell
            "lj_list_sys_info", "lj_nve_create_batch",
            "lj_profile_begin", "lj_profile_end", "lj_tune_set", "lj_tune_get", "lj_last_error"]
 LJ_TUNE_BUILD_LANES, LJ_TUNE_FORCE_BATCH, LJ_TUNE_CELL_DIV, LJ_TUNE_N = 0, 1, 2, 3
-LJ_PROF_CELLS, LJ_PROF_NEIGH, LJ_PROF_FORCE, LJ_PROF_OTHER, LJ_PROF_N = 0, 1, 2, 3, 4
-PROF_PHASES = ("cells", "neigh", "force", "other")
+LJ_PROF_CELLS, LJ_PROF_NEIGH, LJ_PROF_FORCE, LJ_PROF_OTHER, LJ_PROF_INTEGRATE = 0, 1, 2, 3, 4
+LJ_PROF_N = 5
+PROF_PHASES = ("cells", "neigh", "force", "other", "integrate")
 
 
 class LJError(RuntimeError):

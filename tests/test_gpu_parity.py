@@ -196,6 +196,21 @@ def test_lj131k_orders(lj, ctx, oracle, order):
         check_forces(s, forces_to_np(F, 0), E.item(), W.item(), n.item(), ref)
 
 
+def test_lj131k_two_level_reduction(lj, ctx, oracle):
+    """One row per slice (64 lanes per row): 32,768 force blocks, so energy,
+    virial and pair count are summed in two levels (8 spans of 4,096 block
+    partials, then the 8 span sums)."""
+    s = synth.cell_sorted(synth.lj131k())
+    ref = reference(oracle, s)
+    pos = to_dev(s.pos, 0)
+    for kind in (0, 1):
+        nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=kind, lanes=64)
+        assert nl.info().lanes == 64
+        F, E, W, n = lj.lj_forces(ctx, pos, s.box, 1.0, 1.0, s.rc, nl)
+        torch.cuda.synchronize()
+        check_forces(s, forces_to_np(F, 0), E.item(), W.item(), n.item(), ref)
+
+
 def test_lj4m_sampled(lj, ctx, oracle):
     """4,000,000 atoms: forces and full-list rows of 1,500 sampled atoms,
     each computed one by one by the oracle; zero net force over all atoms."""
