@@ -358,8 +358,10 @@ def test_errors(lj, ctx):
     assert e.value.status == lj.LJ_E_INVALID
 
 
-# 35^3 = 42,875 cells: the multi-tile prefix sum with a ragged last tile
-@pytest.mark.parametrize("min_cell,ncell", [(3.3, 4), (0.45, 35)])
+# The prefix sum over the cells: one block up to 32,768 cells (25^3, 30^3),
+# the multi-tile form beyond (35^3, 40^3, 41^3: ragged last tiles)
+@pytest.mark.parametrize("min_cell,ncell", [(3.3, 4), (0.63, 25), (0.52, 30), (0.45, 35),
+                                            (0.395, 40), (0.38, 41)])
 def test_cells_structure(lj, ctx, min_cell, ncell):
     s = synth.permuted(synth.lj4k(), 5)
     pos = to_dev(s.pos, 0)
