@@ -9,7 +9,10 @@ and the same forces -- so tuning is a search over timings:
   cell_div     list-build cells of side (rc + skin) / cell_div (LJ_TUNE_CELL_DIV)
 
 Each candidate is timed with the library's own HIP-event profiler on the
-context's stream (device time of the list-build and force kernels).  Results
+context's stream (device time of the list-build and force kernels) and
+ranked by one objective: build_us, force_us, step_us (a rebuild and a force
+evaluation, the default) or nve_us (the force evaluation plus a tenth of the
+rebuild: a step of the integrator at its default rebuild cadence).  Results
 are cached as JSON keyed by device name, CU count, atom-count bucket,
 density, search length, list kind and precision.
 """

@@ -20,8 +20,9 @@
 // thread of a system's k-th row handles the system's k-th atom in memory
 // order, not the row's atom: the arrays stream instead of being gathered.
 // Every product and sum is rounded on its own, as in the oracle's
-// integrator.  Bytes per atom and step (AoS4): drift or kick alone 208 and
-// 120, the fused kernel 232.
+// integrator.  Bytes per atom (AoS4): drift 208 (reads vel, force, pos 32
+// each and disp 24; writes vel, pos, disp), kick 120 (reads vel, force,
+// disp; writes vel); the fused kernel moves the same 208 as the drift alone.
 #include <math.h>
 
 #include <algorithm>
