@@ -277,10 +277,13 @@ LJ_API lj_status lj_nve_create_batch(lj_ctx* ctx, double* pos, double* vel, doub
 LJ_API lj_status lj_nve_init(lj_nve* nve);
 /* Advance nsteps steps.  use_graph != 0: whole rebuild cycles (rebuild_every
  * steps ending with a rebuild) are captured once into a HIP graph and
- * replayed; the remaining steps run as ordinary launches.  Requires the
- * context's stream to be a created stream (not the null stream) when
- * use_graph != 0.  Asynchronous; list overflow and bad coordinates are
- * reported by lj_sync. */
+ * replayed; the remaining steps run as ordinary launches.  Within a run the
+ * kick that ends a step and the drift that opens the next are one pass over
+ * the atoms; the arithmetic is the same as taking the steps one call at a
+ * time, bit for bit, and vel holds the synchronised velocities when the run
+ * ends.  Requires the context's stream to be a created stream (not the null
+ * stream) when use_graph != 0.  Asynchronous; list overflow and bad
+ * coordinates are reported by lj_sync. */
 LJ_API lj_status lj_nve_run(lj_nve* nve, int32_t nsteps, int32_t use_graph);
 /* Steps taken since lj_nve_init (host counter). */
 LJ_API lj_status lj_nve_steps(const lj_nve* nve, int64_t* steps);

@@ -37,7 +37,8 @@ def from_dev(t, layout):
     return a[:, :3].copy() if layout == 0 else a.T.copy()
 
 
-def run_gpu(lj, ctx, s, dt, nsteps, every, kind, layout, precision=0, use_graph=False):
+def run_gpu(lj, ctx, s, dt, nsteps, every, kind, layout, precision=0, use_graph=False,
+            per_call=None):
     pos, vel = to_dev(s.pos, layout), to_dev(s.vel, layout)
     force = torch.zeros_like(pos)
     torch.cuda.synchronize()
@@ -46,7 +47,14 @@ def run_gpu(lj, ctx, s, dt, nsteps, every, kind, layout, precision=0, use_graph=
         nve = lj.NVE(ctx, pos, vel, force, s.box, 1.0, 1.0, s.rc, nl, dt, every, precision,
                      log_rows=nsteps + 1)
         nve.init()
-        nve.run(nsteps, use_graph=use_graph)
+        if per_call is None:
+            nve.run(nsteps, use_graph=use_graph)
+        else:
+            done = 0
+            while done < nsteps:
+                k = min(per_call, nsteps - done)
+                nve.run(k, use_graph=use_graph)
+                done += k
         ctx.sync()
     torch.cuda.synchronize()
     out = (from_dev(pos, layout), from_dev(vel, layout), from_dev(force, layout),
@@ -89,6 +97,20 @@ def test_nve_graph_equals_eager(lj, ctx):
     for x, y in zip(a[:4], b[:4]):
         assert np.array_equal(x, y)
     assert a[4] == b[4] == 43
+
+
+@pytest.mark.parametrize("layout", [0, 1])
+def test_nve_run_lengths_agree_bitwise(lj, ctx, layout):
+    """A run of 27 steps in one call (the kick ending each step fused with the
+    next drift), in calls of 1 step (no fusion) and in calls of 4 (fused
+    within each call) give the same trajectory and log, bit for bit."""
+    s = state()
+    ref = run_gpu(lj, ctx, s, 0.005, 27, 10, 1, layout)
+    for per_call in (1, 4):
+        got = run_gpu(lj, ctx, s, 0.005, 27, 10, 1, layout, per_call=per_call)
+        for x, y in zip(ref[:4], got[:4]):
+            assert np.array_equal(x, y)
+        assert got[4] == 27
 
 
 def test_nve_graph_replays_repeatedly(lj, ctx):
