@@ -94,6 +94,35 @@ def test_batch_pairs_and_forces(lj, ctx, oracle, kind, layout, build_lanes):
         assert entries == (1 if kind == 0 else 2) * ref.shape[0]
 
 
+def test_batch_two_level_reduction(lj, ctx, oracle):
+    """One row per slice (64 lanes per row): the 19,652-atom system has 4,928
+    force blocks, so every system's energy, virial and pair count are summed
+    in two levels of 2 spans; the small systems' spans are short or empty."""
+    systems = [synth.small_fcc(17, 0.9, 0.05, 3, rc=2.5)] + small_batch(count=5, seed=21)
+    off = offsets(systems)
+    n, box, rc = params(systems)
+    pos = concat(systems)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(ctx.stream):
+        nl = lj.lj_build_neighbors_batch(ctx, pos, n, box, rc, 0.3, kind=1, lanes=64)
+        ones = np.ones(len(systems))
+        F, E, W, C = lj.lj_forces_batch(ctx, pos, nl, ones, ones, rc)
+        ctx.sync()
+    torch.cuda.synchronize()
+    assert nl.info().lanes == 64
+    f = F.cpu().numpy()[:, :3]
+    E, W, C = E.cpu().numpy(), W.cpu().numpy(), C.cpu().numpy()
+    for s, sy in enumerate(systems):
+        rp, col = oracle.cell_pairs(sy.pos, sy.box, sy.rc + sy.skin)
+        Fr, Er, Wr, nr = oracle.forces(sy.pos, sy.box, 1.0, 1.0, sy.rc, rp, col)
+        scale = max(np.abs(Fr).max(), 24.0)
+        assert np.abs(f[off[s]:off[s + 1]] - Fr).max() <= 1e-10 * scale, f"system {s}"
+        assert abs(E[s] - Er) <= 1e-12 * abs(Er), f"system {s}"
+        assert abs(W[s] - Wr) <= 1e-12 * abs(Wr), f"system {s}"
+        assert C[s] == nr, f"system {s}"
+    nl.free()
+
+
 def run_batch_nve(lj, ctx, systems, dt, nsteps, every, use_graph, precision=0):
     n, box, rc = params(systems)
     pos = concat(systems)
