@@ -163,6 +163,7 @@ void list_release(lj_list* l) {
     dfree(l->slice_iters);
     dfree(l->slice_stats);
     dfree(l->acc);
+    dfree(l->q32);
     dfree(l->col);
     dfree(l->stats);
     dfree(l->fc);
@@ -464,7 +465,8 @@ lj_status build_list(lj_ctx* ctx, const double* pos, int32_t layout, int nsys, c
 lj_status set_fconst(lj_ctx* ctx, lj_list* l, const double* eps, const double* sigma,
                      const double* rc) {
     std::vector<lj_fconst> f((size_t)l->nsys);
-    for (int s = 0; s < l->nsys; ++s) f[(size_t)s] = lj_make_fconst(eps[s], sigma[s], rc[s]);
+    for (int s = 0; s < l->nsys; ++s)
+        f[(size_t)s] = lj_make_fconst(eps[s], sigma[s], rc[s], l->hsys[(size_t)s].box);
     if (l->fc_valid && memcmp(f.data(), l->hfc.data(), f.size() * sizeof(lj_fconst)) == 0)
         return LJ_OK;
     l->hfc = f;
@@ -668,6 +670,13 @@ extern "C" lj_status lj_build_neighbors_batch(lj_ctx* ctx, const double* pos, in
     return build_list(ctx, pos, layout, nsys, n, box, rc, skin, kind, lanes, nullptr, list);
 }
 
+// The mixed kernel's fixed-point copy of the positions: allocated on first
+// use, outside any graph capture.
+lj_status lj_list_ensure_q32(lj_list* l) {
+    if (l->q32) return LJ_OK;
+    return dmalloc(&l->q32, l->n);
+}
+
 lj_status lj_list_ensure_cells(lj_ctx* ctx, lj_list* l) {
     if (l->cells) return LJ_OK;
     std::vector<int64_t> n((size_t)l->nsys);
@@ -853,6 +862,7 @@ extern "C" lj_status lj_forces(lj_ctx* ctx, const double* pos, int64_t n, int32_
     DeviceGuard guard(ctx->device);
     lj_list* l = const_cast<lj_list*>(list);
     if ((st = set_fconst(ctx, l, &eps, &sigma, &rc))) return st;
+    if (precision == LJ_MIXED && (st = lj_list_ensure_q32(l))) return st;
     return lj_launch_forces(ctx, pos, layout, precision, l, l->fc, force, energy, virial, npairs);
 }
 
@@ -872,6 +882,7 @@ extern "C" lj_status lj_forces_batch(lj_ctx* ctx, const double* pos, int32_t lay
     DeviceGuard guard(ctx->device);
     lj_list* l = const_cast<lj_list*>(list);
     if ((st = set_fconst(ctx, l, eps, sigma, rc))) return st;
+    if (precision == LJ_MIXED && (st = lj_list_ensure_q32(l))) return st;
     return lj_launch_forces(ctx, pos, layout, precision, l, l->fc, force, energy, virial, npairs);
 }
 
@@ -895,8 +906,10 @@ static lj_status nve_create(lj_ctx* ctx, double* pos, double* vel, double* force
     if ((st = check_params(list->nsys, eps, sigma, rc, list))) return st;
     DeviceGuard guard(ctx->device);
     if ((st = lj_list_ensure_cells(ctx, list))) return st;
+    if (precision == LJ_MIXED && (st = lj_list_ensure_q32(list))) return st;
     std::vector<lj_fconst> f((size_t)list->nsys);
-    for (int s = 0; s < list->nsys; ++s) f[(size_t)s] = lj_make_fconst(eps[s], sigma[s], rc[s]);
+    for (int s = 0; s < list->nsys; ++s)
+        f[(size_t)s] = lj_make_fconst(eps[s], sigma[s], rc[s], list->hsys[(size_t)s].box);
     return lj_nve_make(ctx, pos, vel, force, layout, f.data(), precision, list, dt, rebuild_every,
                        log, log_rows, out);
 }

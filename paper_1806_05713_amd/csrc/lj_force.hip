@@ -22,6 +22,8 @@
 // levels when a system has more than 4096 blocks) and writes
 // E = scale * (sum - count * V(rc)), W = scale * sum, count * scale, with
 // scale = 1/2 for a full list (every pair is visited twice).
+#include <math.h>
+
 #include <algorithm>
 
 #include "lj_internal.h"
@@ -43,6 +45,7 @@ struct ForceArgs {
     double* partials;        // 4 doubles per (logical) block
     double* acc;             // half list: spread force accumulator (3 x 16 n16 doubles)
     int64_t n16;
+    uint4* q32;              // mixed: fixed-point positions (x, y, z as fractions of the box)
 };
 
 __device__ __forceinline__ double r2_rounded(double x, double y, double z) {
@@ -247,6 +250,42 @@ __device__ __forceinline__ void gather_q(const double* __restrict__ pos, int64_t
     }
 }
 
+// Mixed precision: each coordinate as a 32-bit fraction of its box length,
+// u = rint(x 2^32 / L) mod 2^32.  A wrapping 32-bit difference u_j - u_i is
+// then the nearest-image displacement in units of L / 2^32 (1.2e-8 at
+// L = 50.8), exact up to the two roundings of u: one 16-byte record per
+// entry instead of 32, and no image arithmetic.  r^2 is formed in FP64 from
+// it; the pair terms are FP32.  One thread per row of the
+// list; the thread of a system's k-th row converts its k-th atom.
+template <int LAYOUT>
+__global__ __launch_bounds__(LJ_BLOCK) void k_quantize(const double* __restrict__ pos, int64_t n,
+                                                       const lj_sys* sys,
+                                                       const int32_t* slice_sys, int C,
+                                                       const lj_fconst* fc,
+                                                       uint4* __restrict__ q32) {
+    const int64_t r = blockIdx.x * (int64_t)LJ_BLOCK + threadIdx.x;
+    const int sid = __builtin_amdgcn_readfirstlane(
+        slice_sys[(blockIdx.x * (int64_t)LJ_BLOCK) / C]);
+    const lj_sys& sy = sys[sid];
+    const int64_t t = r - sy.slice0 * C;
+    if (t >= sy.n) return;
+    const int64_t i = sy.atom0 + t;
+    double x, y, z;
+    if (LAYOUT == LJ_AOS4) {
+        const double4 q = reinterpret_cast<const double4*>(pos)[i];
+        x = q.x;
+        y = q.y;
+        z = q.z;
+    } else {
+        x = pos[i];
+        y = pos[n + i];
+        z = pos[2 * n + i];
+    }
+    const lj_fconst& f = fc[sid];
+    auto fix = [](double v, double inv) { return (uint32_t)(uint64_t)(int64_t)rint(v * inv); };
+    q32[i] = make_uint4(fix(x, f.qinv[0]), fix(y, f.qinv[1]), fix(z, f.qinv[2]), 0u);
+}
+
 // Loads are issued U entries at a time, and the indices of the next U
 // entries are requested before the current ones are computed, so each
 // wavefront keeps up to 3U gathers and U index loads in flight (the
@@ -291,10 +330,49 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_force(ForceArgs a) {
     int jn[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) jn[u] = idx_at(u);
+    // the force constants as values, read once
+    const double sig2 = fc.sig2, c24 = fc.c24, c48 = fc.c48;
+    const float sig2f = fc.sig2f, c24f = fc.c24f, c48f = fc.c48f;
+    const double qs0 = fc.qs[0], qs1 = fc.qs[1], qs2 = fc.qs[2];
+    const double rc2lo = fc.rc2lo, rc2hi = fc.rc2hi;
+    // mixed: the row atom's fixed-point record; whether the lane met an entry
+    // whose r^2 lies in the quantisation band of rc^2 (decided after the loop)
+    uint4 qi4 = make_uint4(0u, 0u, 0u, 0u);
+    if constexpr (PREC != LJ_FP64) qi4 = a.q32[i];
+    bool had_amb = false;
+    // pair terms of an interacting entry from its r^2 (mixed: FP32 terms)
+    auto pair_terms = [&](double r2, bool m, double& fs, double& sr6d) {
+        if constexpr (PREC == LJ_FP64) {
+            const double ir2 = m ? recip(r2) : 0.0;
+            const double sr2 = sig2 * ir2;
+            const double sr6 = sr2 * sr2 * sr2;
+            fs = ir2 * (sr6 * fma(c48, sr6, -c24));
+            sr6d = sr6;
+        } else {
+            const float ir2 = m ? __builtin_amdgcn_rcpf((float)r2) : 0.0f;
+            const float sr2 = sig2f * ir2;
+            const float sr6 = sr2 * sr2 * sr2;
+            fs = (double)(ir2 * (sr6 * fmaf(c48f, sr6, -c24f)));
+            sr6d = (double)sr6;
+        }
+    };
+    auto fixed_disp = [&](const uint4& qj, double& tx, double& ty, double& tz) {
+        // nearest-image displacement from the wrapping fixed-point
+        // difference: an exact integer times an exact unit, one rounding
+        tx = (double)(int32_t)(qj.x - qi4.x) * qs0;
+        ty = (double)(int32_t)(qj.y - qi4.y) * qs1;
+        tz = (double)(int32_t)(qj.z - qi4.z) * qs2;
+    };
     for (int it0 = 0; it0 < iters; it0 += U) {
         double px[U], py[U], pz[U];
+        uint4 qv[U];
+        if constexpr (PREC == LJ_FP64) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) gather_q<LAYOUT>(a.pos, a.n, jn[u], px[u], py[u], pz[u]);
+            for (int u = 0; u < U; ++u) gather_q<LAYOUT>(a.pos, a.n, jn[u], px[u], py[u], pz[u]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) qv[u] = a.q32[jn[u]];
+        }
         int jc[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) jc[u] = jn[u];
@@ -304,25 +382,25 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_force(ForceArgs a) {
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            double tx = px[u] - qx, ty = py[u] - qy, tz = pz[u] - qz;
-            tx = fma(-rint(tx * ibx), bx, tx);
-            ty = fma(-rint(ty * iby), by, ty);
-            tz = fma(-rint(tz * ibz), bz, tz);
-            const double r2 = r2_rounded(tx, ty, tz);
-            const bool m = (it0 + u < iters) && ((it0 + u) * G < lim) && (r2 < rc2);
-            double fs, sr6d;
-            if (PREC == LJ_FP64) {
-                const double ir2 = m ? recip(r2) : 0.0;
-                const double sr2 = fc.sig2 * ir2;
-                const double sr6 = sr2 * sr2 * sr2;
-                fs = ir2 * (sr6 * fma(fc.c48, sr6, -fc.c24));
-                sr6d = sr6;
+            const bool valid = (it0 + u < iters) && ((it0 + u) * G < lim);
+            double tx, ty, tz, fs, sr6d;
+            bool m;
+            if constexpr (PREC == LJ_FP64) {
+                tx = px[u] - qx;
+                ty = py[u] - qy;
+                tz = pz[u] - qz;
+                tx = fma(-rint(tx * ibx), bx, tx);
+                ty = fma(-rint(ty * iby), by, ty);
+                tz = fma(-rint(tz * ibz), bz, tz);
+                const double r2 = r2_rounded(tx, ty, tz);
+                m = valid && (r2 < rc2);
+                pair_terms(r2, m, fs, sr6d);
             } else {
-                const float ir2 = m ? __builtin_amdgcn_rcpf((float)r2) : 0.0f;
-                const float sr2 = fc.sig2f * ir2;
-                const float sr6 = sr2 * sr2 * sr2;
-                fs = (double)(ir2 * (sr6 * fmaf(fc.c48f, sr6, -fc.c24f)));
-                sr6d = (double)sr6;
+                fixed_disp(qv[u], tx, ty, tz);
+                const double r2 = r2_rounded(tx, ty, tz);
+                m = valid && (r2 < rc2lo);
+                had_amb = had_amb || (valid && !(r2 < rc2lo) && (r2 < rc2hi));
+                pair_terms(r2, m, fs, sr6d);
             }
             // energy and virial from two sums: sum (sigma/r)^12 and sum (sigma/r)^6
             sA = fma(sr6d, sr6d, sA);
@@ -332,6 +410,37 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_force(ForceArgs a) {
             fy = fma(-fs, ty, fy);
             fz = fma(-fs, tz, fz);
             if (HALF && m) acc_add(a.acc, a.n16, jc[u], fs * tx, fs * ty, fs * tz);
+        }
+    }
+    if constexpr (PREC != LJ_FP64) {
+        // rare: entries whose fixed-point r^2 fell within the band around rc^2,
+        // decided on the unquantised positions as in the FP64 kernel
+        if (__builtin_amdgcn_ballot_w64(had_amb) != 0 && had_amb) {
+            for (int it = 0; it < iters && it * G < lim; ++it) {
+                const int j = idx_at(it);
+                double tx, ty, tz;
+                fixed_disp(a.q32[j], tx, ty, tz);
+                const double r2 = r2_rounded(tx, ty, tz);
+                if (r2 < rc2lo || !(r2 < rc2hi)) continue;
+                double ex, ey, ez;
+                gather_q<LAYOUT>(a.pos, a.n, j, ex, ey, ez);
+                ex = ex - qx;
+                ey = ey - qy;
+                ez = ez - qz;
+                ex = fma(-rint(ex * ibx), bx, ex);
+                ey = fma(-rint(ey * iby), by, ey);
+                ez = fma(-rint(ez * ibz), bz, ez);
+                if (!(r2_rounded(ex, ey, ez) < rc2)) continue;
+                double fs, sr6d;
+                pair_terms(r2, true, fs, sr6d);
+                sA = fma(sr6d, sr6d, sA);
+                sB += sr6d;
+                cnt += 1;
+                fx = fma(-fs, tx, fx);
+                fy = fma(-fs, ty, fy);
+                fz = fma(-fs, tz, fz);
+                if (HALF) acc_add(a.acc, a.n16, j, fs * tx, fs * ty, fs * tz);
+            }
         }
     }
     // sum the row over its G lanes
@@ -412,8 +521,8 @@ int64_t lj_force_partials(const lj_list* l) {
     return lj_force_blocks(l->nslices) + (split > 1 ? (int64_t)l->nsys * split : 0);
 }
 
-lj_fconst lj_make_fconst(double eps, double sigma, double rc) {
-    lj_fconst f;
+lj_fconst lj_make_fconst(double eps, double sigma, double rc, const double box[3]) {
+    lj_fconst f = {};
     f.rc2 = rc * rc;
     f.sig2 = sigma * sigma;
     f.c4 = 4.0 * eps;
@@ -426,6 +535,25 @@ lj_fconst lj_make_fconst(double eps, double sigma, double rc) {
     f.c4f = (float)f.c4;
     f.c24f = (float)f.c24;
     f.c48f = (float)f.c48;
+    // Fixed point for the mixed kernel, and the band around rc^2 in which its
+    // r^2 defers to the test on the unquantised positions.  A displacement
+    // component from the fixed-point records is off by at most one unit
+    // s = L / 2^32 (two roundings of half a unit; the product by the exact
+    // unit adds one FP64 rounding): e <= 1.0001 s.  Its r^2 then differs from
+    // that of the unquantised positions by at most 2 sqrt(3) r e + 3 e^2 for r
+    // up to 1.001 rc (beyond that both tests reject); the band is twice that
+    // bound plus a margin for the FP64 roundings of either r^2.
+    const double two32 = 4294967296.0;
+    double smax = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        f.qinv[d] = two32 / box[d];
+        f.qs[d] = box[d] / two32;
+        smax = std::max(smax, f.qs[d]);
+    }
+    const double rx = 1.001 * rc, e = 1.0001 * smax;
+    const double band = 2.0 * (2.0 * sqrt(3.0) * rx * e + 3.0 * e * e) + 1e-12 * f.rc2;
+    f.rc2lo = f.rc2 - band;
+    f.rc2hi = f.rc2 + band;
     return f;
 }
 
@@ -451,10 +579,25 @@ lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int preci
     a.col = l->col;
     a.partials = ctx->partials;
     a.acc = l->acc;
+    a.q32 = l->q32;
     a.n16 = (l->n + 15) / 16;
+    if (precision != LJ_FP64 && !l->q32)
+        return lj_fail(LJ_E_INVALID, "mixed precision without the list's fixed-point buffer");
     lj_status st;
     {
         lj_prof_scope prof(ctx, LJ_PROF_FORCE);
+        if (precision != LJ_FP64) {
+            const dim3 qgrid((unsigned)(l->nslices * (LJ_WAVE / l->lanes) / LJ_BLOCK));
+            if (layout == LJ_AOS4)
+                hipLaunchKernelGGL(k_quantize<LJ_AOS4>, qgrid, dim3(LJ_BLOCK), 0, ctx->stream,
+                                   pos, l->n, (const lj_sys*)l->dsys, (const int32_t*)l->slice_sys,
+                                   LJ_WAVE / l->lanes, fc, l->q32);
+            else
+                hipLaunchKernelGGL(k_quantize<LJ_SOA>, qgrid, dim3(LJ_BLOCK), 0, ctx->stream,
+                                   pos, l->n, (const lj_sys*)l->dsys, (const int32_t*)l->slice_sys,
+                                   LJ_WAVE / l->lanes, fc, l->q32);
+            LJ_HIP(hipGetLastError());
+        }
         // entries in flight per lane: tuned value
         const int u = ctx->tune[LJ_TUNE_FORCE_BATCH];
 #define LJ_U(G)                                                                      \

@@ -71,6 +71,13 @@ struct lj_sys {
 struct lj_fconst {
     double rc2, sig2, c4, c24, c48, vc;   // rc^2, sigma^2, 4 eps, 24 eps, 48 eps, V(rc)
     float sig2f, c4f, c24f, c48f;
+    // Mixed precision: positions as 32-bit fixed point, x = u * L / 2^32
+    double qinv[3];        // 2^32 / L per dimension (quantisation)
+    double qs[3];          // L / 2^32 per dimension: one fixed-point unit (exact)
+    // An r^2 of fixed-point displacements below rc2lo interacts and at or
+    // above rc2hi does not, whatever the test on the unquantised positions
+    // gives; in between that test decides
+    double rc2lo, rc2hi;
 };
 
 // Device status words of a context.
@@ -159,6 +166,7 @@ struct lj_list {
     bool fc_valid;
     lj_cells* cells;               // owned cell structure for in-place rebuilds (lazy)
     double* acc;                   // half list: spread force accumulator, zero between calls
+    uint4* q32;                    // mixed precision: fixed-point positions (n records, lazy)
 };
 
 // ---------------------------------------------------------------- errors
@@ -188,9 +196,12 @@ int64_t lj_force_blocks(int64_t nslices);
 // (double4) the context must hold for list l.
 int lj_force_split(const lj_list* l);
 int64_t lj_force_partials(const lj_list* l);
+// LJ_MIXED needs the list's fixed-point position buffer (lj_list_ensure_q32,
+// called before any launch that a graph may capture).
 lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int precision,
                            const lj_list* l, const lj_fconst* fc, double* force, double* energy,
                            double* virial, int64_t* npairs);
+lj_status lj_list_ensure_q32(lj_list* l);
 // integrator (lj_nve.hip)
 lj_status lj_nve_make(lj_ctx* ctx, double* pos, double* vel, double* force, int32_t layout,
                       const lj_fconst* hfc, int32_t precision, lj_list* list, double dt,
@@ -205,8 +216,8 @@ lj_status lj_list_ensure_cells(lj_ctx* ctx, lj_list* l);
 lj_status lj_launch_scan(hipStream_t s, int32_t* in, int32_t* out, int64_t m, int32_t* work,
                          bool clear_in);
 lj_status lj_launch_zero(hipStream_t s, void* p, int64_t bytes);
-// host: force constants of one system
-lj_fconst lj_make_fconst(double eps, double sigma, double rc);
+// host: force constants of one system with box lengths box[3]
+lj_fconst lj_make_fconst(double eps, double sigma, double rc, const double box[3]);
 
 // ------------------------------------------------------- device helpers
 // Logical block index that gives each XCD a contiguous range of blocks

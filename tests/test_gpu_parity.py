@@ -605,6 +605,54 @@ def test_pairs_around_rs_in_the_fp32_band(lj, ctx, oracle):
         assert np.array_equal(canon(sel), ref[0])
 
 
+@pytest.mark.parametrize("layout", [0, 1])
+def test_mixed_pairs_around_rc_in_the_fp32_band(lj, ctx, oracle, layout):
+    """125 isolated pairs at distances spread over the band where the mixed
+    kernel's FP32 r^2 (from fixed-point positions) defers to the FP64 test
+    (r within ~1e-6 relative of rc) and around it, some across periodic
+    faces: the mixed kernel counts exactly the oracle's interacting pairs, and
+    its forces stay within 1e-5 of the scale."""
+    rc, skin = 3.0, 0.3
+    L = 40.0
+    rng = np.random.Generator(np.random.PCG64(2025))
+    k = 5
+    site = L / k
+    rel = np.concatenate([np.linspace(-3e-6, 3e-6, 121), [0.0, 1e-16, -1e-16, 2e-16]])
+    pts = []
+    for n, (ix, iy, iz) in enumerate(np.ndindex(k, k, k)):
+        a = (np.array([ix, iy, iz]) + rng.uniform(0.3, 0.7, 3)) * site
+        if n % 7 == 0:
+            a[n % 3] = L - 0.5
+        u = rng.normal(size=3)
+        u /= np.linalg.norm(u)
+        r = rc * (1.0 + rel[n])
+        if rel[n] == 1e-16:
+            r = np.nextafter(rc, 0.0)
+        elif rel[n] == -1e-16:
+            r = np.nextafter(rc, 10.0)
+        elif rel[n] == 2e-16:
+            r = rc
+        pts += [a, a + r * u]
+    s = synth.System(pos=synth.wrap(np.array(pts), L), box=np.array([L, L, L]), rc=rc,
+                     skin=skin, name="rcband")
+    ref = reference(oracle, s)
+    assert 0 < ref[4] < 125                     # some pairs interact, some do not
+    pos = to_dev(s.pos, layout)
+    for kind in (0, 1):
+        nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=kind)
+        F, E, W, n = lj.lj_forces(ctx, pos, s.box, 1.0, 1.0, s.rc, nl, precision=lj.LJ_MIXED)
+        torch.cuda.synchronize()
+        assert n.item() == ref[4]
+        _, Fr, Er, Wr, nr = ref
+        scale = max(np.abs(Fr).max(), 24.0)
+        assert np.abs(forces_to_np(F, layout) - Fr).max() <= 1e-5 * scale
+        # pairs at rc carry almost no shifted energy: compare on the scale of
+        # the shift count * |V(rc)| rather than relative to the near-zero sum
+        vc = abs(4.0 * ((1.0 / rc) ** 12 - (1.0 / rc) ** 6))
+        assert abs(E.item() - Er) <= 1e-6 * (nr * vc + abs(Er))
+        assert abs(W.item() - Wr) <= 1e-6 * abs(Wr)
+
+
 def test_atom_count_limit(lj, ctx):
     """More than LJ_MAX_ATOMS atoms is refused before any device memory is
     touched (kernels address records with 32-bit byte offsets)."""
