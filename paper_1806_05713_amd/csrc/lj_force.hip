@@ -282,8 +282,7 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_quantize(const double* __restrict_
         z = pos[2 * n + i];
     }
     const lj_fconst& f = fc[sid];
-    auto fix = [](double v, double inv) { return (uint32_t)(uint64_t)(int64_t)rint(v * inv); };
-    q32[i] = make_uint4(fix(x, f.qinv[0]), fix(y, f.qinv[1]), fix(z, f.qinv[2]), 0u);
+    q32[i] = make_uint4(lj_fix32(x, f.qinv[0]), lj_fix32(y, f.qinv[1]), lj_fix32(z, f.qinv[2]), 0u);
 }
 
 // Loads are issued U entries at a time, and the indices of the next U
@@ -559,7 +558,7 @@ lj_fconst lj_make_fconst(double eps, double sigma, double rc, const double box[3
 
 lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int precision,
                            const lj_list* l, const lj_fconst* fc, double* force, double* energy,
-                           double* virial, int64_t* npairs) {
+                           double* virial, int64_t* npairs, bool quantized) {
     const int64_t blocks = lj_force_blocks(l->nslices);
     if (lj_force_partials(l) > ctx->partials_cap)
         return lj_fail(LJ_E_INVALID, "context partials too small");
@@ -586,7 +585,7 @@ lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int preci
     lj_status st;
     {
         lj_prof_scope prof(ctx, LJ_PROF_FORCE);
-        if (precision != LJ_FP64) {
+        if (precision != LJ_FP64 && !quantized) {
             const dim3 qgrid((unsigned)(l->nslices * (LJ_WAVE / l->lanes) / LJ_BLOCK));
             if (layout == LJ_AOS4)
                 hipLaunchKernelGGL(k_quantize<LJ_AOS4>, qgrid, dim3(LJ_BLOCK), 0, ctx->stream,

@@ -197,10 +197,16 @@ int64_t lj_force_blocks(int64_t nslices);
 int lj_force_split(const lj_list* l);
 int64_t lj_force_partials(const lj_list* l);
 // LJ_MIXED needs the list's fixed-point position buffer (lj_list_ensure_q32,
-// called before any launch that a graph may capture).
+// called before any launch that a graph may capture); `quantized`: the buffer
+// already holds pos in fixed point (written by the integrator's drift).
 lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int precision,
                            const lj_list* l, const lj_fconst* fc, double* force, double* energy,
-                           double* virial, int64_t* npairs);
+                           double* virial, int64_t* npairs, bool quantized = false);
+// host and device: one coordinate in the mixed kernel's fixed point,
+// rint(x 2^32 / L) mod 2^32
+__host__ __device__ __forceinline__ uint32_t lj_fix32(double x, double inv_unit) {
+    return (uint32_t)(uint64_t)(int64_t)rint(x * inv_unit);
+}
 lj_status lj_list_ensure_q32(lj_list* l);
 // integrator (lj_nve.hip)
 lj_status lj_nve_make(lj_ctx* ctx, double* pos, double* vel, double* force, int32_t layout,

@@ -95,6 +95,8 @@ struct RowArgs {
     int C;                 // rows per slice
     double* partials;
     int64_t* dstep;
+    uint4* q32;            // mixed precision: fixed-point copy written by the drift (or NULL)
+    const lj_fconst* fc;   // per system: the fixed-point unit
 };
 
 // Half kick, drift and displacement update of one atom (record index i).
@@ -117,6 +119,11 @@ __device__ __forceinline__ void drift_atom(const RowArgs& a, const lj_sys& sy, i
     }
     store_rec<LAYOUT>(a.vel, a.n, i, v);
     store_rec<LAYOUT>(a.pos, a.n, i, x);
+    if (a.q32) {
+        const double* inv = a.fc[&sy - a.sys].qinv;   // sy is an element of a.sys
+        a.q32[i] = make_uint4(lj_fix32(x.v[0], inv[0]), lj_fix32(x.v[1], inv[1]),
+                              lj_fix32(x.v[2], inv[2]), 0u);
+    }
 }
 
 // Half kick of one atom; returns its kinetic energy and |disp|^2.
@@ -273,12 +280,15 @@ RowArgs row_args(lj_nve* s) {
     a.C = LJ_WAVE / s->list->lanes;
     a.partials = s->partials;
     a.dstep = s->dstep;
+    a.q32 = s->precision != LJ_FP64 ? s->list->q32 : nullptr;
+    a.fc = s->fc;
     return a;
 }
 
-lj_status forces(lj_nve* s) {
+// after a drift the mixed kernel's fixed-point copy is already current
+lj_status forces(lj_nve* s, bool after_drift) {
     return lj_launch_forces(s->ctx, s->pos, s->layout, s->precision, s->list, s->fc, s->force,
-                            s->pe_w, s->pe_w + s->nsys, s->npairs);
+                            s->pe_w, s->pe_w + s->nsys, s->npairs, after_drift);
 }
 
 lj_status log_row(lj_nve* s, int back) {
@@ -324,7 +334,7 @@ lj_status enqueue_chain(lj_nve* s, int64_t first, int64_t count) {
             if ((st = lj_launch_cells(ctx, s->pos, s->layout, l->cells))) return st;
             if ((st = lj_launch_neighbors(ctx, l->cells, l, false))) return st;
         }
-        if ((st = forces(s))) return st;
+        if ((st = forces(s, true))) return st;
     }
     {
         lj_prof_scope prof(ctx, LJ_PROF_INTEGRATE);
@@ -436,7 +446,7 @@ lj_status lj_nve_start(lj_nve* s) {
     if ((st = lj_launch_zero(ctx->stream, s->disp, s->list->n * 3 * (int64_t)sizeof(double))))
         return st;
     hipLaunchKernelGGL(k_set_step, dim3(1), dim3(1), 0, ctx->stream, s->dstep, (int64_t)0);
-    if ((st = forces(s))) return st;
+    if ((st = forces(s, false))) return st;
     // kinetic energy of the initial velocities: a kick of zero length
     const dim3 grid((unsigned)s->rblocks), block(LJ_BLOCK);
     if (s->layout == LJ_AOS4)

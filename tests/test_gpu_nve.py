@@ -113,6 +113,32 @@ def test_nve_run_lengths_agree_bitwise(lj, ctx, layout):
         assert got[4] == 27
 
 
+@pytest.mark.parametrize("layout", [0, 1])
+def test_nve_mixed_forces_match_a_fresh_evaluation(lj, ctx, layout):
+    """In a mixed-precision run the drift writes the force kernel's fixed-point
+    positions itself; the forces the run ends with equal, bit for bit, a
+    fresh mixed evaluation at the final positions (which converts them with
+    its own kernel)."""
+    s = state()
+    pos, vel = to_dev(s.pos, layout), to_dev(s.vel, layout)
+    force = torch.zeros_like(pos)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(ctx.stream):
+        nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=1)
+        nve = lj.NVE(ctx, pos, vel, force, s.box, 1.0, 1.0, s.rc, nl, 0.005, 10, lj.LJ_MIXED,
+                     log_rows=16)
+        nve.init()
+        nve.run(15)
+        F, E, W, n = lj.lj_forces(ctx, pos, s.box, 1.0, 1.0, s.rc, nl, lj.LJ_MIXED)
+        ctx.sync()
+    torch.cuda.synchronize()
+    assert torch.equal(force, F)
+    log = nve.log.cpu().numpy()
+    assert log[15, 0] == E.item() and log[15, 2] == W.item() and log[15, 4] == n.item()
+    nve.free()
+    nl.free()
+
+
 def test_nve_graph_replays_repeatedly(lj, ctx):
     """Replay a captured cycle many times with eager work and syncs between
     replays; every replay must equal the eager run."""
