@@ -81,10 +81,13 @@ typedef enum {
 #define LJ_LIST_FULL 1   /* each pair in both rows; no atomics, every row owns its sum */
 /* precisions */
 #define LJ_FP64 0        /* every operation in FP64 */
-#define LJ_MIXED 1       /* displacement, r^2 and the cutoff test in FP64; the pair
-                            terms ((sigma/r)^2, ^6, the force factor and pair energy)
-                            in FP32; per-atom force, energy and virial accumulated
-                            in FP64 */
+#define LJ_MIXED 1       /* positions read as 32-bit fixed point in the box (the
+                            displacement is off by at most L / 2^32 per component);
+                            r^2 in FP64 and the cutoff test exact (the same pairs as
+                            LJ_FP64); the pair terms ((sigma/r)^2, ^6, the force
+                            factor and pair energy) in FP32; per-atom force, energy
+                            and virial accumulated in FP64.  Needs n x 16 bytes
+                            more device memory per list (allocated on first use) */
 /* position / force layouts */
 #define LJ_AOS4 0
 #define LJ_SOA 1
