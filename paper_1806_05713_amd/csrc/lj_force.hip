@@ -16,6 +16,11 @@
 //   F_i   -= fs t;  half list: F_j += fs t by atomic add (Newton's third law)
 //   A     += (sigma/r)^12, B += (sigma/r)^6, count += mask, so that
 //            E = 4 eps (A - B) - count V(rc) and W = sum fs r^2 = 24 eps (2A - B)
+// Mixed precision (LJ_MIXED) gathers 16-byte fixed-point records instead
+// (k_quantize writes them): t is the wrapping integer difference times the
+// unit L / 2^32, r^2 stays FP64, and the few entries whose r^2 falls within
+// the quantisation band around rc^2 are decided on the FP64 positions after
+// the main loop; the pair terms are FP32.
 // The row's force is summed over its G lanes with cross-lane shuffles.
 // Energy, virial and the pair count are summed per block in a fixed order,
 // and one block per system sums the block partials in a fixed order (in two

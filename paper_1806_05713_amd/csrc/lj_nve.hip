@@ -19,6 +19,8 @@
 // each inside one system), so every block knows its system and box, but the
 // thread of a system's k-th row handles the system's k-th atom in memory
 // order, not the row's atom: the arrays stream instead of being gathered.
+// In a mixed-precision run the drift also writes the force kernel's
+// fixed-point positions, so the forces that follow need no conversion pass.
 // Every product and sum is rounded on its own, as in the oracle's
 // integrator.  Bytes per atom (AoS4): drift 208 (reads vel, force, pos 32
 // each and disp 24; writes vel, pos, disp), kick 120 (reads vel, force,
