@@ -94,6 +94,37 @@ def test_batch_pairs_and_forces(lj, ctx, oracle, kind, layout, build_lanes):
         assert entries == (1 if kind == 0 else 2) * ref.shape[0]
 
 
+@pytest.mark.parametrize("layout", [0, 1])
+def test_batch_mixed_forces(lj, ctx, oracle, layout):
+    """Mixed precision over a batch: each system's fixed-point unit and
+    cutoff band come from its own box and rc; every system's pair count is
+    the oracle's exactly and its forces are within 1e-5 of the scale."""
+    systems = small_batch(count=12, seed=31)
+    off = offsets(systems)
+    n, box, rc = params(systems)
+    pos = concat(systems, layout)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(ctx.stream):
+        nl = lj.lj_build_neighbors_batch(ctx, pos, n, box, rc, 0.3, kind=1)
+        ones = np.ones(len(systems))
+        F, E, W, C = lj.lj_forces_batch(ctx, pos, nl, ones, ones, rc, precision=lj.LJ_MIXED)
+        ctx.sync()
+    torch.cuda.synchronize()
+    f = F.cpu().numpy()
+    f = f[:, :3] if layout == 0 else f.T
+    E, W, C = E.cpu().numpy(), W.cpu().numpy(), C.cpu().numpy()
+    for s, sy in enumerate(systems):
+        rp, col = oracle.cell_pairs(sy.pos, sy.box, sy.rc + sy.skin)
+        Fr, Er, Wr, nr = oracle.forces(sy.pos, sy.box, 1.0, 1.0, sy.rc, rp, col)
+        scale = max(np.abs(Fr).max(), 24.0)
+        assert np.abs(f[off[s]:off[s + 1]] - Fr).max() <= 1e-5 * scale, f"system {s}"
+        # FP32 pair terms over a few hundred atoms: less averaging than at 4k
+        assert abs(E[s] - Er) <= 5e-6 * abs(Er), f"system {s}"
+        assert abs(W[s] - Wr) <= 5e-6 * abs(Wr), f"system {s}"
+        assert C[s] == nr, f"system {s}"
+    nl.free()
+
+
 def test_batch_two_level_reduction(lj, ctx, oracle):
     """One row per slice (64 lanes per row): the 19,652-atom system has 4,928
     force blocks, so every system's energy, virial and pair count are summed
