@@ -219,6 +219,17 @@ def main():
     per = {k: (v[0] / max(v[1], 1) * 1e3) for k, v in prof.items()}   # us per launch
     ms_force_only, _ = time_steps(torch, force_only, args.steps, 2)
 
+    # the same whole step with the mixed-precision force kernel (fixed-point
+    # gathers, FP32 pair terms); the pair set is the FP64 one
+    force_m = torch.empty_like(pos)
+
+    def step_mixed():
+        lj.lj_update_neighbors(ctx, pos, s.box, nl)
+        lj.lj_forces(ctx, pos, s.box, 1.0, 1.0, s.rc, nl, lj.LJ_MIXED, force_m, out)
+
+    ms_step_mixed, _ = time_steps(torch, step_mixed, args.steps, args.warmup)
+    ctx.sync()
+
     force_us = per["force"]
     neigh_us = per["neigh"]
     default_shape = (args.order == "cellsorted" and args.lanes in (0, 8) and
@@ -296,6 +307,9 @@ def main():
         "roofline": roofline,
         "roofline_force": roofline_force,
         "roofline_neigh": roofline_neigh,
+        "mixed_step": {"ms_per_step": round(ms_step_mixed, 6),
+                       "pairs_per_s": round(npairs / (ms_step_mixed * 1e-3), 1),
+                       "speedup_over_fp64": round(ms_step / ms_step_mixed, 3)},
         "force_only": {"us": round(ms_force_only * 1e3, 3),
                        "pairs_per_s": round(npairs / (ms_force_only * 1e-3), 1),
                        "alg_GBps": round(bytes_force / (ms_force_only * 1e-3) / 1e9, 1)},
