@@ -235,9 +235,20 @@ __global__ __launch_bounds__(1024) void k_log(const double* __restrict__ partial
     const lj_sys& sy = sys[s];
     const int64_t b0 = sy.slice0 * C / LJ_BLOCK, b1 = (sy.slice0 + sy.nslices) * C / LJ_BLOCK;
     double ke = 0.0, d2 = 0.0;
-    for (int64_t b = b0 + threadIdx.x; b < b1; b += 1024) {
-        ke += partials[2 * b];
-        d2 = fmax(d2, partials[2 * b + 1]);
+    // four partials per thread and pass, loaded before they are added (the
+    // order of the sums is fixed by the thread and the pass)
+    for (int64_t bb = b0 + threadIdx.x; bb < b1; bb += 4 * 1024) {
+        double2 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t b = bb + u * 1024;
+            v[u] = b < b1 ? reinterpret_cast<const double2*>(partials)[b] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ke += v[u].x;
+            d2 = fmax(d2, v[u].y);
+        }
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
