@@ -154,8 +154,8 @@ def main():
                          "500k-atom fluid (use --steps to shorten)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              "(the path shards by spatial domains across GPUs, which is not built here)",
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the "
+              "library runs on a single GPU: sharding by spatial domains is not implemented)",
               file=sys.stderr)
         sys.exit(2)
 
