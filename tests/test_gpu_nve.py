@@ -139,6 +139,34 @@ def test_nve_mixed_forces_match_a_fresh_evaluation(lj, ctx, layout):
     nl.free()
 
 
+def test_nve_log_sums_many_row_blocks(lj, ctx):
+    """1,149,984 atoms (4,492 row blocks of 256, so the log kernel sums its
+    partials in several passes): after 3 steps the logged kinetic energy is
+    sum v^2/2 of the velocities the run returns, and the logged potential
+    energy, virial and pair count are those of a fresh evaluation at the
+    final positions."""
+    s = synth.small_fcc(66, 0.85, 0.05, 61, rc=2.5, T=1.0)
+    assert s.n == 1_149_984
+    pos, vel = to_dev(s.pos, 0), to_dev(s.vel, 0)
+    force = torch.zeros_like(pos)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(ctx.stream):
+        nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=1)
+        nve = lj.NVE(ctx, pos, vel, force, s.box, 1.0, 1.0, s.rc, nl, 0.005, 10, log_rows=4)
+        nve.init()
+        nve.run(3)
+        F, E, W, n = lj.lj_forces(ctx, pos, s.box, 1.0, 1.0, s.rc, nl)
+        ctx.sync()
+    torch.cuda.synchronize()
+    log = nve.log.cpu().numpy()
+    v = from_dev(vel, 0)
+    ke = 0.5 * np.sum(v * v)
+    assert abs(log[3, 1] - ke) <= 1e-12 * ke
+    assert log[3, 0] == E.item() and log[3, 2] == W.item() and log[3, 4] == n.item()
+    nve.free()
+    nl.free()
+
+
 def test_nve_graph_replays_repeatedly(lj, ctx):
     """Replay a captured cycle many times with eager work and syncs between
     replays; every replay must equal the eager run."""
