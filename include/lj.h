@@ -86,8 +86,11 @@ typedef enum {
                             r^2 in FP64 and the cutoff test exact (the same pairs as
                             LJ_FP64); the pair terms ((sigma/r)^2, ^6, the force
                             factor and pair energy) in FP32; per-atom force, energy
-                            and virial accumulated in FP64.  Needs n x 16 bytes
-                            more device memory per list (allocated on first use) */
+                            and virial accumulated in FP64.  The quantisation adds a
+                            relative force error of about 13 (L / 2^32) / r: ~1e-7
+                            for L ~ 100 sigma, near 1e-5 for L ~ 3,000 sigma (use
+                            LJ_FP64 for such boxes).  Needs n x 16 bytes more device
+                            memory per list (allocated on first use) */
 /* position / force layouts */
 #define LJ_AOS4 0
 #define LJ_SOA 1
