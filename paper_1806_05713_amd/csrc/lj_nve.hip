@@ -24,7 +24,8 @@
 // Every product and sum is rounded on its own, as in the oracle's
 // integrator.  Bytes per atom (AoS4): drift 208 (reads vel, force, pos 32
 // each and disp 24; writes vel, pos, disp), kick 120 (reads vel, force,
-// disp; writes vel); the fused kernel moves the same 208 as the drift alone.
+// disp; writes vel); the fused kernel moves the same 208 as the drift alone,
+// 224 in a mixed run (the 16-byte fixed-point record).
 #include <math.h>
 
 #include <algorithm>
