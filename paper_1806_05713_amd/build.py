@@ -21,7 +21,7 @@ OUT = os.path.join(PKG, "liblj.so")
 BUILD = os.path.join(PKG, "_build")
 
 SOURCES = ["lj_api.hip", "lj_cells.hip", "lj_neigh.hip", "lj_force.hip", "lj_nve.hip"]
-HEADERS = ["lj_internal.h"]
+HEADERS = ["lj_internal.h", "lj_force_loop.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -31,91 +31,12 @@
 
 #include <algorithm>
 
+#include "lj_force_loop.h"
 #include "lj_internal.h"
 
 namespace {
 
-struct ForceArgs {
-    const double* pos;
-    double* force;
-    int64_t n;               // atoms over all systems (SoA stride)
-    int64_t nslices;
-    const lj_sys* sys;
-    const lj_fconst* fc;
-    const int32_t* slice_sys;
-    const int32_t* row_atom;
-    const int32_t* row_len;
-    const int32_t* slice_iters;
-    const int32_t* col;
-    double* partials;        // 4 doubles per (logical) block
-    double* acc;             // half list: spread force accumulator (3 x 16 n16 doubles)
-    int64_t n16;
-    uint4* q32;              // mixed: fixed-point positions (x, y, z as fractions of the box)
-};
-
-__device__ __forceinline__ double r2_rounded(double x, double y, double z) {
-#pragma clang fp contract(off)
-    return (x * x + y * y) + z * z;
-}
-
-template <int LAYOUT>
-__device__ __forceinline__ void load_q(const double* __restrict__ pos, int64_t n, int64_t i,
-                                       double& x, double& y, double& z) {
-    if (LAYOUT == LJ_AOS4) {
-        const double4 q = reinterpret_cast<const double4*>(pos)[i];
-        x = q.x;
-        y = q.y;
-        z = q.z;
-    } else {
-        x = pos[i];
-        y = pos[n + i];
-        z = pos[2 * n + i];
-    }
-}
-
-template <int LAYOUT>
-__device__ __forceinline__ void add_f(double* __restrict__ f, int64_t n, int64_t i, double x,
-                                      double y, double z) {
-    if (LAYOUT == LJ_AOS4) {
-        unsafeAtomicAdd(f + 4 * i + 0, x);
-        unsafeAtomicAdd(f + 4 * i + 1, y);
-        unsafeAtomicAdd(f + 4 * i + 2, z);
-    } else {
-        unsafeAtomicAdd(f + i, x);
-        unsafeAtomicAdd(f + n + i, y);
-        unsafeAtomicAdd(f + 2 * n + i, z);
-    }
-}
-
-// Half list: the Newton's-third-law scatter goes into an accumulator with
-// one block per component, so that the three atomics of a pair do not queue
-// on one cache line.
-__device__ __forceinline__ int64_t spread_at(int64_t i, int64_t n16) { return i; }
-__device__ __forceinline__ void acc_add(double* __restrict__ acc, int64_t n16, int64_t i,
-                                        double x, double y, double z) {
-    const int64_t s = spread_at(i, n16);
-    unsafeAtomicAdd(acc + s, x);
-    unsafeAtomicAdd(acc + 16 * n16 + s, y);
-    unsafeAtomicAdd(acc + 32 * n16 + s, z);
-}
-
-template <int LAYOUT>
-__device__ __forceinline__ void store_f(double* __restrict__ f, int64_t n, int64_t i, double x,
-                                        double y, double z) {
-    if (LAYOUT == LJ_AOS4) {
-        reinterpret_cast<double4*>(f)[i] = make_double4(x, y, z, 0.0);
-    } else {
-        f[i] = x;
-        f[n + i] = y;
-        f[2 * n + i] = z;
-    }
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, LJ_WAVE);
-    return v;
-}
+using namespace ljf;
 
 // Block partials (E, W, count) -> partials[4 * block], summed in a fixed
 // order.  No atomics: a device-scope atomic must stay coherent across the
@@ -227,34 +148,6 @@ __global__ __launch_bounds__(1024) void k_force_reduce(const double4* __restrict
     }
 }
 
-// 1/x as v_rcp_f64 refined by two Newton steps y <- y (2 - x y) (each step
-// squares the relative error, which v_rcp_f64 already bounds far below 2^-20).
-__device__ __forceinline__ double recip(double x) {
-    double y = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
-    return fma(y, e, y);
-}
-
-template <int LAYOUT>
-__device__ __forceinline__ void gather_q(const double* __restrict__ pos, int64_t n, int j,
-                                         double& x, double& y, double& z) {
-    if (LAYOUT == LJ_AOS4) {
-        // 32-bit byte offset from a uniform base: one dwordx4 + one dwordx2 load
-        const double4* q = reinterpret_cast<const double4*>(
-            reinterpret_cast<const char*>(pos) + (uint32_t)j * 32u);
-        x = q->x;
-        y = q->y;
-        z = q->z;
-    } else {
-        const uint32_t o = (uint32_t)j * 8u;
-        x = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(pos) + o);
-        y = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(pos + n) + o);
-        z = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(pos + 2 * n) + o);
-    }
-}
-
 // Mixed precision: each coordinate as a 32-bit fraction of its box length,
 // u = rint(x 2^32 / L) mod 2^32.  A wrapping 32-bit difference u_j - u_i is
 // then the nearest-image displacement in units of L / 2^32 (1.2e-8 at
@@ -290,192 +183,30 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_quantize(const double* __restrict_
     q32[i] = make_uint4(lj_fix32(x, f.qinv[0]), lj_fix32(y, f.qinv[1]), lj_fix32(z, f.qinv[2]), 0u);
 }
 
-// Loads are issued U entries at a time, and the indices of the next U
-// entries are requested before the current ones are computed, so each
-// wavefront keeps up to 3U gathers and U index loads in flight (the
-// load/compute overlap that software pipelining gives a CPU core).
+// One wavefront per slice; a block's four slices belong to one system
+// (systems own whole 256-row blocks).
 template <int G, bool HALF, int LAYOUT, int PREC, int U>
 __global__ __launch_bounds__(LJ_BLOCK) void k_force(ForceArgs a) {
-    constexpr int C = LJ_WAVE / G;
-    const int lane = threadIdx.x & (LJ_WAVE - 1);
     const int64_t blk = lj_xcd_block(blockIdx.x, gridDim.x);
     const int slice = __builtin_amdgcn_readfirstlane(
         (int)blk * LJ_WAVES_PER_BLOCK + (threadIdx.x >> 6));
-    // a block's four slices belong to one system (systems own whole 256-row blocks)
     const int sid = __builtin_amdgcn_readfirstlane(a.slice_sys[blk * LJ_WAVES_PER_BLOCK]);
-    const lj_sys& sy = a.sys[sid];
-    const lj_fconst& fc = a.fc[sid];
-    const int iters = __builtin_amdgcn_readfirstlane(a.slice_iters[slice]);
-    const int c = lane / G, g = lane % G;
-    const int64_t r = (int64_t)slice * C + c;
-    const int i = a.row_atom[r];
-    const int lim = a.row_len[r] - g;   // entry it*G + g is inside the row iff it*G < lim
-    const bool row_ok = (r - sy.slice0 * C) < sy.n;
-    const double bx = sy.box[0], by = sy.box[1], bz = sy.box[2];
-    const double ibx = sy.inv_box[0], iby = sy.inv_box[1], ibz = sy.inv_box[2];
-    const double rc2 = fc.rc2;
-    double qx, qy, qz;
-    gather_q<LAYOUT>(a.pos, a.n, i, qx, qy, qz);
-
-    const char* colbase = reinterpret_cast<const char*>(
-        a.col + sy.col0 + (int64_t)(slice - sy.slice0) * (sy.cap / G) * LJ_WAVE);
-    const uint32_t lane_off = (uint32_t)lane * 4u;
-    double fx = 0.0, fy = 0.0, fz = 0.0, sA = 0.0, sB = 0.0;
-    int cnt = 0;
-
-    // slot of step `it`, clamped into the slice so that every index load is
-    // unconditional (no branch for the compiler to wait behind)
-    const int last = iters > 0 ? iters - 1 : 0;
-    auto idx_at = [&](int it) -> int {
-        const int k = it < last ? it : last;
-        return __builtin_nontemporal_load(
-            reinterpret_cast<const int*>(colbase + (uint32_t)(k * LJ_WAVE * 4) + lane_off));
-    };
-    int jn[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) jn[u] = idx_at(u);
-    // the force constants as values, read once
-    const double sig2 = fc.sig2, c24 = fc.c24, c48 = fc.c48;
-    const float sig2f = fc.sig2f, c24f = fc.c24f, c48f = fc.c48f;
-    const double qs0 = fc.qs[0], qs1 = fc.qs[1], qs2 = fc.qs[2];
-    const double rc2lo = fc.rc2lo, rc2hi = fc.rc2hi;
-    // mixed: the row atom's fixed-point record; whether the lane met an entry
-    // whose r^2 lies in the quantisation band of rc^2 (decided after the loop)
-    uint4 qi4 = make_uint4(0u, 0u, 0u, 0u);
-    if constexpr (PREC != LJ_FP64) qi4 = a.q32[i];
-    bool had_amb = false;
-    // pair terms of an interacting entry from its r^2 (mixed: FP32 terms)
-    auto pair_terms = [&](double r2, bool m, double& fs, double& sr6d) {
-        if constexpr (PREC == LJ_FP64) {
-            const double ir2 = m ? recip(r2) : 0.0;
-            const double sr2 = sig2 * ir2;
-            const double sr6 = sr2 * sr2 * sr2;
-            fs = ir2 * (sr6 * fma(c48, sr6, -c24));
-            sr6d = sr6;
-        } else {
-            const float ir2 = m ? __builtin_amdgcn_rcpf((float)r2) : 0.0f;
-            const float sr2 = sig2f * ir2;
-            const float sr6 = sr2 * sr2 * sr2;
-            fs = (double)(ir2 * (sr6 * fmaf(c48f, sr6, -c24f)));
-            sr6d = (double)sr6;
-        }
-    };
-    auto fixed_disp = [&](const uint4& qj, double& tx, double& ty, double& tz) {
-        // nearest-image displacement from the wrapping fixed-point
-        // difference: an exact integer times an exact unit, one rounding
-        tx = (double)(int32_t)(qj.x - qi4.x) * qs0;
-        ty = (double)(int32_t)(qj.y - qi4.y) * qs1;
-        tz = (double)(int32_t)(qj.z - qi4.z) * qs2;
-    };
-    for (int it0 = 0; it0 < iters; it0 += U) {
-        double px[U], py[U], pz[U];
-        uint4 qv[U];
-        if constexpr (PREC == LJ_FP64) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) gather_q<LAYOUT>(a.pos, a.n, jn[u], px[u], py[u], pz[u]);
-        } else {
-#pragma unroll
-            for (int u = 0; u < U; ++u) qv[u] = a.q32[jn[u]];
-        }
-        int jc[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) jc[u] = jn[u];
-#pragma unroll
-        for (int u = 0; u < U; ++u) jn[u] = idx_at(it0 + U + u);
-        // keep the next indices' loads issued here, ahead of the arithmetic
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool valid = (it0 + u < iters) && ((it0 + u) * G < lim);
-            double tx, ty, tz, fs, sr6d;
-            bool m;
-            if constexpr (PREC == LJ_FP64) {
-                tx = px[u] - qx;
-                ty = py[u] - qy;
-                tz = pz[u] - qz;
-                tx = fma(-rint(tx * ibx), bx, tx);
-                ty = fma(-rint(ty * iby), by, ty);
-                tz = fma(-rint(tz * ibz), bz, tz);
-                const double r2 = r2_rounded(tx, ty, tz);
-                m = valid && (r2 < rc2);
-                pair_terms(r2, m, fs, sr6d);
-            } else {
-                fixed_disp(qv[u], tx, ty, tz);
-                const double r2 = r2_rounded(tx, ty, tz);
-                m = valid && (r2 < rc2lo);
-                had_amb = had_amb || (valid && !(r2 < rc2lo) && (r2 < rc2hi));
-                pair_terms(r2, m, fs, sr6d);
-            }
-            // energy and virial from two sums: sum (sigma/r)^12 and sum (sigma/r)^6
-            sA = fma(sr6d, sr6d, sA);
-            sB += sr6d;
-            cnt += m ? 1 : 0;
-            fx = fma(-fs, tx, fx);
-            fy = fma(-fs, ty, fy);
-            fz = fma(-fs, tz, fz);
-            if (HALF && m) acc_add(a.acc, a.n16, jc[u], fs * tx, fs * ty, fs * tz);
-        }
-    }
-    if constexpr (PREC != LJ_FP64) {
-        // rare: entries whose fixed-point r^2 fell within the band around rc^2,
-        // decided on the unquantised positions as in the FP64 kernel
-        if (__builtin_amdgcn_ballot_w64(had_amb) != 0 && had_amb) {
-            for (int it = 0; it < iters && it * G < lim; ++it) {
-                const int j = idx_at(it);
-                double tx, ty, tz;
-                fixed_disp(a.q32[j], tx, ty, tz);
-                const double r2 = r2_rounded(tx, ty, tz);
-                if (r2 < rc2lo || !(r2 < rc2hi)) continue;
-                double ex, ey, ez;
-                gather_q<LAYOUT>(a.pos, a.n, j, ex, ey, ez);
-                ex = ex - qx;
-                ey = ey - qy;
-                ez = ez - qz;
-                ex = fma(-rint(ex * ibx), bx, ex);
-                ey = fma(-rint(ey * iby), by, ey);
-                ez = fma(-rint(ez * ibz), bz, ez);
-                if (!(r2_rounded(ex, ey, ez) < rc2)) continue;
-                double fs, sr6d;
-                pair_terms(r2, true, fs, sr6d);
-                sA = fma(sr6d, sr6d, sA);
-                sB += sr6d;
-                cnt += 1;
-                fx = fma(-fs, tx, fx);
-                fy = fma(-fs, ty, fy);
-                fz = fma(-fs, tz, fz);
-                if (HALF) acc_add(a.acc, a.n16, j, fs * tx, fs * ty, fs * tz);
-            }
-        }
-    }
-    // sum the row over its G lanes
-#pragma unroll
-    for (int d = G / 2; d >= 1; d >>= 1) {
-        fx += __shfl_xor(fx, d, LJ_WAVE);
-        fy += __shfl_xor(fy, d, LJ_WAVE);
-        fz += __shfl_xor(fz, d, LJ_WAVE);
-    }
-    if (g == 0 && row_ok) {
-        if (HALF)
-            acc_add(a.acc, a.n16, i, fx, fy, fz);
-        else
-            store_f<LAYOUT>(a.force, a.n, i, fx, fy, fz);
-    }
-    // per lane: 4 eps (A - B) and 24 eps (2A - B)
-    block_partials(a, blk, fc.c4 * (sA - sB), fc.c24 * (2.0 * sA - sB), (double)cnt);
+    double e, w, c;
+    slice_forces<G, HALF, LAYOUT, PREC, U>(a, slice, sid, e, w, c);
+    block_partials(a, blk, e, w, c);
 }
 
-// Half list: the forces from the spread accumulator, which is cleared for
-// the next evaluation.
+// Half list: the forces from the accumulator, which is cleared for the next
+// evaluation.
 template <int LAYOUT>
 __global__ __launch_bounds__(LJ_BLOCK) void k_acc_out(double* __restrict__ acc, int64_t n16,
                                                       int64_t n, double* __restrict__ f) {
     const int64_t i = blockIdx.x * (int64_t)LJ_BLOCK + threadIdx.x;
     if (i >= n) return;
-    const int64_t s = spread_at(i, n16);
-    const double x = acc[s], y = acc[16 * n16 + s], z = acc[32 * n16 + s];
-    acc[s] = 0.0;
-    acc[16 * n16 + s] = 0.0;
-    acc[32 * n16 + s] = 0.0;
+    const double x = acc[i], y = acc[16 * n16 + i], z = acc[32 * n16 + i];
+    acc[i] = 0.0;
+    acc[16 * n16 + i] = 0.0;
+    acc[32 * n16 + i] = 0.0;
     store_f<LAYOUT>(f, n, i, x, y, z);
 }
 
