@@ -1,7 +1,8 @@
 // lj_force_loop.h -- the force loop over one slice of the wavefront-sliced
-// Verlet list (Alg. 1 inside the sorted-list loop of Alg. 3), shared by the
-// force kernel and by the list build when it evaluates the forces of the
-// slices it has just built.  Device code only; included by HIP sources.
+// Verlet list (Alg. 1 inside the sorted-list loop of Alg. 3): the body of the
+// force kernel, kept apart from its launch and reductions so that another
+// kernel can evaluate the forces of a slice with the same arithmetic.
+// Device code only; included by HIP sources.
 #pragma once
 
 #include "lj_internal.h"
