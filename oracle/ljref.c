@@ -13,6 +13,10 @@
 #include <stdlib.h>
 #include <string.h>
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
 /* ---------------------------------------------------------------- geometry */
 
 /* Minimum-image component of q_j - q_i in a periodic box of side L (Sec. II:
@@ -267,18 +271,64 @@ static double lj_shift(double eps, double sigma, double rc) {
     return 4.0 * eps * s6 * (s6 - 1.0);
 }
 
+/* Magnitude of the pair force at rc, Fc = -V'(rc) = 24 eps (sigma/rc)^6
+ * [2 (sigma/rc)^6 - 1] / rc: what the force-shifted truncation subtracts. */
+static double lj_force_at(double eps, double sigma, double rc) {
+    double s2 = (sigma * sigma) / (rc * rc);
+    double s6 = s2 * s2 * s2;
+    return 24.0 * eps * s6 * (2.0 * s6 - 1.0) / rc;
+}
+
+/* Parameters of the truncated potential. */
+typedef struct {
+    double eps, sig2, rc, rc2, vc, fc;
+    int trunc;
+} lj_par;
+
+static int make_par(lj_par* p, double eps, double sigma, double rc, int trunc) {
+    if (!(eps > 0.0) || !(sigma > 0.0) || !isfinite(eps) || !isfinite(sigma) || !(rc > 0.0) ||
+        !isfinite(rc))
+        return LJREF_E_INVALID;
+    if (trunc != LJREF_TRUNC_SHIFT && trunc != LJREF_TRUNC_FORCE_SHIFT) return LJREF_E_INVALID;
+    p->eps = eps;
+    p->sig2 = sigma * sigma;
+    p->rc = rc;
+    p->rc2 = rc * rc;
+    p->vc = lj_shift(eps, sigma, rc);
+    p->fc = lj_force_at(eps, sigma, rc);
+    p->trunc = trunc;
+    return LJREF_OK;
+}
+
+/* Alg. 1 for one pair at squared distance r2 < rc^2, with sigma and eps kept
+ * general: fs = -(dV/dr)/r, so that the force on j is +fs t and on i -fs t
+ * (t points from i to j), and e, the pair's truncated energy.
+ *   simple truncation (the paper's, Sec. III.A): V(r) - V(rc), force unchanged;
+ *   force-shifted truncation (the remedy Sec. III.A recommends, in which the
+ *   force also vanishes at rc): V(r) - V(rc) + (r - rc) Fc, force F(r) - Fc. */
+static void pair_terms(const lj_par* p, double r2, double* fs, double* e) {
+    const double sr2 = p->sig2 / r2;
+    const double sr6 = sr2 * sr2 * sr2;
+    double f = 24.0 * p->eps * sr6 * (2.0 * sr6 - 1.0) / r2;
+    double v = 4.0 * p->eps * sr6 * (sr6 - 1.0) - p->vc;
+    if (p->trunc == LJREF_TRUNC_FORCE_SHIFT) {
+        const double r = sqrt(r2);
+        f = f - p->fc / r;
+        v = v + (r - p->rc) * p->fc;
+    }
+    *fs = f;
+    *e = v;
+}
+
 int ljref_forces(int64_t n, const double* pos, const double* box, double eps, double sigma,
-                 double rc, const int64_t* row_ptr, const int32_t* col, double* force,
+                 double rc, int trunc, const int64_t* row_ptr, const int32_t* col, double* force,
                  double* energy, double* virial, int64_t* n_in) {
     int st = check_args(n, pos, box, rc);
     if (st) return st;
     if (row_ptr == NULL || force == NULL || energy == NULL || virial == NULL || n_in == NULL)
         return LJREF_E_INVALID;
-    if (!(eps > 0.0) || !(sigma > 0.0) || !isfinite(eps) || !isfinite(sigma))
-        return LJREF_E_INVALID;
-    const double rc2 = rc * rc;
-    const double sig2 = sigma * sigma;
-    const double vc = lj_shift(eps, sigma, rc);
+    lj_par par;
+    if ((st = make_par(&par, eps, sigma, rc, trunc))) return st;
     for (int64_t k = 0; k < 3 * n; ++k) force[k] = 0.0;
     ksum E = {0.0, 0.0}, W = {0.0, 0.0};
     int64_t count = 0;
@@ -292,12 +342,9 @@ int ljref_forces(int64_t n, const double* pos, const double* box, double eps, do
             const int32_t j = col[k];
             double t[3];
             const double r2 = displacement(qi, pos + 3 * (int64_t)j, box, t);
-            if (!(r2 < rc2)) continue;
-            /* Alg. 1 with sigma, eps kept general: (sigma/r)^2, ^6, and
-             * fs = -(dV/dr)/r = 24 eps (sigma/r)^6 [2 (sigma/r)^6 - 1] / r^2. */
-            const double sr2 = sig2 / r2;
-            const double sr6 = sr2 * sr2 * sr2;
-            const double fs = 24.0 * eps * sr6 * (2.0 * sr6 - 1.0) / r2;
+            if (!(r2 < par.rc2)) continue;
+            double fs, e;
+            pair_terms(&par, r2, &fs, &e);
             /* t points from i to j: the force on j is +fs t, on i it is -fs t. */
             fi[0] -= fs * t[0];
             fi[1] -= fs * t[1];
@@ -305,7 +352,7 @@ int ljref_forces(int64_t n, const double* pos, const double* box, double eps, do
             force[3 * (int64_t)j + 0] += fs * t[0];
             force[3 * (int64_t)j + 1] += fs * t[1];
             force[3 * (int64_t)j + 2] += fs * t[2];
-            ksum_add(&E, 4.0 * eps * sr6 * (sr6 - 1.0) - vc);
+            ksum_add(&E, e);
             ksum_add(&W, fs * r2);
             ++count;
         }
@@ -319,22 +366,142 @@ int ljref_forces(int64_t n, const double* pos, const double* box, double eps, do
     return LJREF_OK;
 }
 
+/* ---------------------------------------------------------- the full list */
+
+int ljref_full_pairs(int64_t n, const int64_t* row_ptr, const int32_t* col, int64_t* frow_ptr,
+                     int32_t* fcol) {
+    if (n < 1 || !row_ptr || !frow_ptr || (row_ptr[n] > 0 && (!col || !fcol)))
+        return LJREF_E_INVALID;
+    /* row lengths of the full list: each half-list pair (i, j) adds one entry
+     * to row i and one to row j */
+    for (int64_t i = 0; i <= n; ++i) frow_ptr[i] = 0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            frow_ptr[i + 1]++;
+            frow_ptr[(int64_t)col[k] + 1]++;
+        }
+    for (int64_t i = 0; i < n; ++i) frow_ptr[i + 1] += frow_ptr[i];
+    int64_t* fill = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    if (!fill) return LJREF_E_NOMEM;
+    memcpy(fill, frow_ptr, (size_t)n * sizeof(int64_t));
+    /* in ascending i: row j receives its partners i < j in ascending order,
+     * then row i its own j > i in ascending order -- every row ends sorted */
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) fcol[fill[col[k]]++] = (int32_t)i;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) fcol[fill[i]++] = col[k];
+    free(fill);
+    /* the two passes above interleave within a row only if a row held j < i,
+     * which a half list does not; sort anyway so the order is the stated one */
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t a = frow_ptr[i] + 1; a < frow_ptr[i + 1]; ++a) {
+            int32_t v = fcol[a];
+            int64_t b = a - 1;
+            while (b >= frow_ptr[i] && fcol[b] > v) {
+                fcol[b + 1] = fcol[b];
+                --b;
+            }
+            fcol[b + 1] = v;
+        }
+    }
+    return LJREF_OK;
+}
+
+int ljref_forces_full(int64_t n, const double* pos, const double* box, double eps, double sigma,
+                      double rc, int trunc, const int64_t* row_ptr, const int32_t* col,
+                      double* force, double* energy, double* virial, int64_t* n_in) {
+    int st = check_args(n, pos, box, rc);
+    if (st) return st;
+    if (row_ptr == NULL || force == NULL || energy == NULL || virial == NULL || n_in == NULL)
+        return LJREF_E_INVALID;
+    lj_par par;
+    if ((st = make_par(&par, eps, sigma, rc, trunc))) return st;
+    double* erow = (double*)malloc((size_t)n * sizeof(double));
+    double* wrow = (double*)malloc((size_t)n * sizeof(double));
+    int64_t* crow = (int64_t*)malloc((size_t)n * sizeof(int64_t));
+    if (!erow || !wrow || !crow) {
+        free(erow);
+        free(wrow);
+        free(crow);
+        return LJREF_E_NOMEM;
+    }
+    /* Every row owns its force: F_i = -sum_j fs t (no scatter to j), so rows
+     * are independent and the loop over them may run on any number of
+     * threads with the same result.  Each row's energy and virial are its
+     * own compensated sums, added afterwards in row order. */
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+        const double* qi = pos + 3 * i;
+        double fi[3] = {0.0, 0.0, 0.0};
+        ksum E = {0.0, 0.0}, W = {0.0, 0.0};
+        int64_t c = 0;
+        for (int64_t k = row_ptr[i]; k < row_ptr[i + 1]; ++k) {
+            double t[3];
+            const double r2 = displacement(qi, pos + 3 * (int64_t)col[k], box, t);
+            if (!(r2 < par.rc2)) continue;
+            double fs, e;
+            pair_terms(&par, r2, &fs, &e);
+            fi[0] -= fs * t[0];
+            fi[1] -= fs * t[1];
+            fi[2] -= fs * t[2];
+            ksum_add(&E, e);
+            ksum_add(&W, fs * r2);
+            ++c;
+        }
+        force[3 * i + 0] = fi[0];
+        force[3 * i + 1] = fi[1];
+        force[3 * i + 2] = fi[2];
+        erow[i] = ksum_get(&E);
+        wrow[i] = ksum_get(&W);
+        crow[i] = c;
+    }
+    /* every pair is visited from both of its rows */
+    ksum E = {0.0, 0.0}, W = {0.0, 0.0};
+    int64_t count = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        ksum_add(&E, erow[i]);
+        ksum_add(&W, wrow[i]);
+        count += crow[i];
+    }
+    *energy = 0.5 * ksum_get(&E);
+    *virial = 0.5 * ksum_get(&W);
+    *n_in = count / 2;
+    free(erow);
+    free(wrow);
+    free(crow);
+    return LJREF_OK;
+}
+
+int ljref_set_threads(int nthreads) {
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+    return omp_get_max_threads();
+#else
+    (void)nthreads;
+    return 1;
+#endif
+}
+
 /* ------------------------------------------------------------ per-atom sample */
 
 int ljref_sample(int64_t n, const double* pos, const double* box, double eps, double sigma,
-                 double rc, double rs, int64_t ns, const int64_t* idx, double* f, double* e,
-                 double* w, int64_t* nrs, int32_t* rows, int64_t rowcap) {
+                 double rc, int trunc, double rs, int64_t ns, const int64_t* idx, double* f,
+                 double* e, double* w, int64_t* nrs, int32_t* rows, int64_t rowcap) {
     int st = check_args(n, pos, box, rs);
     if (st) return st;
     if (!(rc > 0.0) || rc > rs || ns < 0 || (ns > 0 && (!idx || !f || !e || !w || !nrs)))
         return LJREF_E_INVALID;
+    lj_par par;
+    if ((st = make_par(&par, eps, sigma, rc, trunc))) return st;
     for (int64_t s = 0; s < ns; ++s)
         if (idx[s] < 0 || idx[s] >= n) return LJREF_E_INVALID;
     cell_grid g;
     st = grid_build(&g, n, pos, box, rs);
     if (st) return st;
-    const double rc2 = rc * rc, rs2 = rs * rs, sig2 = sigma * sigma;
-    const double vc = lj_shift(eps, sigma, rc);
+    const double rs2 = rs * rs;
+    /* Each sampled atom is found and summed on its own (the grid is only
+     * read), so the loop may run on any number of threads with the same result. */
+#pragma omp parallel for schedule(dynamic, 64)
     for (int64_t s = 0; s < ns; ++s) {
         const int64_t i = idx[s];
         const double* qi = pos + 3 * i;
@@ -353,14 +520,13 @@ int ljref_sample(int64_t n, const double* pos, const double* box, double eps, do
                     if (row && m < rowcap) row[m] = (int32_t)j;
                     ++m;
                 }
-                if (!(r2 < rc2)) continue;
-                const double sr2 = sig2 / r2;
-                const double sr6 = sr2 * sr2 * sr2;
-                const double fs = 24.0 * eps * sr6 * (2.0 * sr6 - 1.0) / r2;
+                if (!(r2 < par.rc2)) continue;
+                double fs, ep;
+                pair_terms(&par, r2, &fs, &ep);
                 fi[0] -= fs * t[0];
                 fi[1] -= fs * t[1];
                 fi[2] -= fs * t[2];
-                ksum_add(&E, 4.0 * eps * sr6 * (sr6 - 1.0) - vc);
+                ksum_add(&E, ep);
                 ksum_add(&W, fs * r2);
             }
         }
@@ -404,14 +570,19 @@ static int build_list(int64_t n, const double* pos, const double* box, double rs
 }
 
 int ljref_nve(int64_t n, double* pos, double* vel, const double* box, double eps, double sigma,
-              double rc, double skin, double dt, int32_t nsteps, int32_t rebuild_every,
-              double* log, double* force) {
+              double rc, int trunc, double skin, double dt, int32_t nsteps,
+              int32_t rebuild_every, double* log, double* force) {
     const double rs = rc + skin;
     int st = check_args(n, pos, box, rs);
     if (st) return st;
-    if (!vel || !log || !force || nsteps < 0 || rebuild_every < 1 || !(skin >= 0.0) ||
+    if (!vel || !log || !force || nsteps < 0 || rebuild_every < 0 || !(skin >= 0.0) ||
         !isfinite(dt))
         return LJREF_E_INVALID;
+    /* Sec. III.B: the list stays valid while no pair has closed in by more
+     * than the margin rs - rc = skin, which holds while every atom has moved
+     * less than skin/2 since the build.  The displacement-triggered mode
+     * rebuilds at the first step whose largest displacement exceeds that. */
+    const double half_skin2 = (0.5 * skin) * (0.5 * skin);
     int64_t* row_ptr = (int64_t*)malloc((size_t)(n + 1) * sizeof(int64_t));
     double* disp = (double*)calloc((size_t)(3 * n), sizeof(double));
     int64_t cap = 64 * n + 1024;
@@ -425,11 +596,15 @@ int ljref_nve(int64_t n, double* pos, double* vel, const double* box, double eps
     st = build_list(n, pos, box, rs, row_ptr, &col, &cap);
     double pe = 0.0, vir = 0.0;
     int64_t nin = 0;
-    if (!st) st = ljref_forces(n, pos, box, eps, sigma, rc, row_ptr, col, force, &pe, &vir, &nin);
+    if (!st)
+        st = ljref_forces(n, pos, box, eps, sigma, rc, trunc, row_ptr, col, force, &pe, &vir,
+                          &nin);
     for (int32_t step = 0; !st && step <= nsteps; ++step) {
+        int rebuilt = step == 0;
         if (step > 0) {
             for (int64_t k = 0; k < 3 * n; ++k) vel[k] += 0.5 * dt * force[k];
-            for (int64_t i = 0; i < n; ++i)
+            double dmax = 0.0;
+            for (int64_t i = 0; i < n; ++i) {
                 for (int d = 0; d < 3; ++d) {
                     const double dx = dt * vel[3 * i + d];
                     double x = pos[3 * i + d] + dx;
@@ -438,12 +613,18 @@ int ljref_nve(int64_t n, double* pos, double* vel, const double* box, double eps
                     if (x >= box[d]) x = 0.0;
                     pos[3 * i + d] = x;
                 }
-            if (step % rebuild_every == 0) {
+                const double* u = disp + 3 * i;
+                const double d2 = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
+                if (d2 > dmax) dmax = d2;
+            }
+            rebuilt = rebuild_every > 0 ? step % rebuild_every == 0 : dmax > half_skin2;
+            if (rebuilt) {
                 st = build_list(n, pos, box, rs, row_ptr, &col, &cap);
                 if (st) break;
                 for (int64_t k = 0; k < 3 * n; ++k) disp[k] = 0.0;
             }
-            st = ljref_forces(n, pos, box, eps, sigma, rc, row_ptr, col, force, &pe, &vir, &nin);
+            st = ljref_forces(n, pos, box, eps, sigma, rc, trunc, row_ptr, col, force, &pe, &vir,
+                              &nin);
             if (st) break;
             for (int64_t k = 0; k < 3 * n; ++k) vel[k] += 0.5 * dt * force[k];
         }
@@ -456,11 +637,12 @@ int ljref_nve(int64_t n, double* pos, double* vel, const double* box, double eps
             const double d2 = (u[0] * u[0] + u[1] * u[1]) + u[2] * u[2];
             if (d2 > dmax) dmax = d2;
         }
-        log[5 * step + 0] = pe;
-        log[5 * step + 1] = ksum_get(&K);
-        log[5 * step + 2] = vir;
-        log[5 * step + 3] = sqrt(dmax);
-        log[5 * step + 4] = (double)nin;
+        log[6 * step + 0] = pe;
+        log[6 * step + 1] = ksum_get(&K);
+        log[6 * step + 2] = vir;
+        log[6 * step + 3] = sqrt(dmax);
+        log[6 * step + 4] = (double)nin;
+        log[6 * step + 5] = (double)rebuilt;
     }
     free(row_ptr);
     free(disp);

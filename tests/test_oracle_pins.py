@@ -356,3 +356,253 @@ def test_nve_fluctuation_shrinks_with_dt(oracle):
     e1 = l1[:, 0] + l1[:, 1]
     e2 = l2[:, 0] + l2[:, 1]
     assert np.std(e2) < 0.6 * np.std(e1)
+
+
+# ---------------------------------------------------------------------------
+# Force-shifted truncation (Sec. III.A: the truncation with force and energy
+# both vanishing at rc).  Pinned by continuity at rc, F = -grad E, the virial
+# as a scaling derivative, and a lattice sum by direct enumeration.
+# ---------------------------------------------------------------------------
+FS = 1   # oracle.ljref.TRUNC_FORCE_SHIFT
+
+
+@pytest.mark.parametrize("eps,sigma", [(1.0, 1.0), (0.7, 1.3)])
+@pytest.mark.parametrize("across_face", [False, True])
+def test_force_shifted_vanishes_at_rc(oracle, eps, sigma, across_face):
+    rc = 2.5 * sigma
+    pos, box = two_atoms(rc * (1.0 - 1e-9), 1, L=max(10.0, 2.5 * rc), across_face=across_face)
+    rp = np.array([0, 1, 1], dtype=np.int64)
+    col = np.array([1], dtype=np.int32)
+    F, E, W, n = oracle.forces(pos, box, eps, sigma, rc, rp, col, trunc=FS)
+    assert n == 1
+    # force and energy go to zero continuously (the simple truncation leaves
+    # a force jump of |F(rc)| ~ 0.039 eps/sigma at rc = 2.5 sigma)
+    assert np.abs(F).max() < 1e-8 * eps / sigma
+    assert abs(E) < 1e-15 * eps + 1e-16
+    F0, E0, _, n0 = oracle.forces(pos, box, eps, sigma, rc, rp, col)
+    assert n0 == 1 and np.abs(F0).max() > 1e-2 * eps / sigma
+    # beyond rc: nothing
+    pos2, box2 = two_atoms(rc * (1.0 + 1e-9), 1, L=max(10.0, 2.5 * rc), across_face=across_face)
+    F2, E2, W2, n2 = oracle.forces(pos2, box2, eps, sigma, rc, rp, col, trunc=FS)
+    assert n2 == 0 and E2 == 0.0 and W2 == 0.0 and np.all(F2 == 0.0)
+
+
+def test_force_shifted_pair_energy_is_integral_of_force(oracle):
+    # E(r) = integral from r to rc of F(s) ds for the force-shifted pair,
+    # checked at the points of a grid by Simpson's rule on the oracle's own
+    # forces over each remaining interval.
+    rc = 3.0
+    rs = np.linspace(1.0, rc * (1 - 1e-12), 4001)     # 4000 intervals
+    rp = np.array([0, 1, 1], dtype=np.int64)
+    col = np.array([1], dtype=np.int32)
+    Fr, Er = [], []
+    for r in rs:
+        pos, box = two_atoms(r, 2, L=10.0)
+        F, E, _, _ = oracle.forces(pos, box, 1.0, 1.0, rc, rp, col, trunc=FS)
+        Fr.append(F[1, 2])
+        Er.append(E)
+    Fr, Er = np.array(Fr), np.array(Er)
+    h = rs[1] - rs[0]
+    # Simpson over pairs of intervals: integral from rs[2m] to rc
+    seg = h / 3.0 * (Fr[0:-2:2] + 4.0 * Fr[1:-1:2] + Fr[2::2])
+    tail = np.concatenate([np.cumsum(seg[::-1])[::-1], [0.0]])
+    assert np.abs(tail - Er[::2]).max() < 1e-7 * np.abs(Er).max()
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_force_shifted_is_minus_gradient(oracle, seed):
+    s = synth.small_fcc(5, 1.0, 0.15, seed, rc=2.5)
+    rng = np.random.Generator(np.random.PCG64(seed + 300))
+    h = 1e-6
+    rp, col = oracle.cell_pairs(s.pos, s.box, s.rc + s.skin)
+    F, _, _, _ = oracle.forces(s.pos, s.box, 1.0, 1.0, s.rc, rp, col, trunc=FS)
+
+    def local(p, i):
+        f, e, w, nrs, _ = oracle.sample(p, s.box, 1.0, 1.0, s.rc, s.rc, np.array([i]), trunc=FS)
+        return 2.0 * e[0], f[0]
+
+    for i in rng.choice(s.n, size=10, replace=False):
+        _, fi = local(s.pos, i)
+        np.testing.assert_allclose(F[i], fi, rtol=0, atol=1e-12 * max(1.0, np.abs(fi).max()))
+        for d in range(3):
+            p = s.pos.copy()
+            p[i, d] += h
+            ep, _ = local(p, i)
+            p[i, d] -= 2 * h
+            em, _ = local(p, i)
+            # no pair needs skipping: the force-shifted energy is C1 across rc
+            fd = -(ep - em) / (2 * h)
+            assert fd == pytest.approx(F[i, d], abs=2e-6 * max(1.0, abs(F[i, d])))
+
+
+def test_force_shifted_virial_is_minus_scaling_derivative(oracle):
+    s = synth.small_fcc(6, 0.9, 0.12, 3)
+    rp, col = oracle.cell_pairs(s.pos, s.box, s.rc + s.skin)
+    _, E0, W, n0 = oracle.forces(s.pos, s.box, 1.0, 1.0, s.rc, rp, col, trunc=FS)
+    h = 1e-7
+    _, Ep, _, _ = oracle.forces(s.pos * (1 + h), s.box * (1 + h), 1.0, 1.0, s.rc, rp, col, trunc=FS)
+    _, Em, _, _ = oracle.forces(s.pos * (1 - h), s.box * (1 - h), 1.0, 1.0, s.rc, rp, col, trunc=FS)
+    fd = -(Ep - Em) / (2 * h)
+    assert fd == pytest.approx(W, rel=1e-6)
+
+
+def lattice_energy_force_shifted(rho, rc):
+    """E/N of a perfect FCC crystal with the force-shifted pair energy, by
+    enumerating lattice vectors: V(r) - V(rc) - (r - rc) V'(rc)."""
+    a = (4.0 / rho) ** (1.0 / 3.0)
+    basis = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]]) * a
+    m = int(math.ceil(rc / a)) + 1
+    g = np.arange(-m, m + 1) * a
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    cells = np.stack([X.ravel(), Y.ravel(), Z.ravel()], axis=1)
+    R = (cells[:, None, :] + basis[None, :, :]).reshape(-1, 3)
+    r = np.sqrt(np.sum(R * R, axis=1))
+    r = r[(r > 0) & (r < rc)]
+    V = lambda x: 4.0 * (x ** -12 - x ** -6)
+    dV = lambda x: -48.0 * x ** -13 + 24.0 * x ** -7
+    v = V(r) - V(rc) - (r - rc) * dV(rc)
+    return 0.5 * math.fsum(v.tolist())
+
+
+@pytest.mark.parametrize("rho,rc,n", [(1.0, 3.0, 6), (0.85, 2.5, 5)])
+def test_force_shifted_lattice_sum(oracle, rho, rc, n):
+    s = synth.small_fcc(n, rho, 0.0, 0, rc=rc)
+    rp, col = oracle.cell_pairs(s.pos, s.box, rc + 0.3)
+    F, E, W, nin = oracle.forces(s.pos, s.box, 1.0, 1.0, rc, rp, col, trunc=FS)
+    assert np.abs(F).max() < 1e-11
+    assert E / s.n == pytest.approx(lattice_energy_force_shifted(rho, rc), rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# The full-list force loop and the per-atom sampler against the half list.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", ["lj4k", "disordered", "vac-nc1"])
+@pytest.mark.parametrize("trunc", [0, FS])
+def test_full_list_forces_equal_half_list(oracle, name, trunc):
+    maker = {c[0]: c[1] for c in CASES}[name]
+    s = maker()
+    rp, col = oracle.cell_pairs(s.pos, s.box, s.rc + s.skin)
+    frp, fcol = oracle.full_pairs(rp, col)
+    # the full list holds each half-list pair in both rows, rows sorted
+    ij = half_pairs_set(rp, col)
+    full = np.concatenate([ij, ij[:, ::-1]])
+    full = full[np.lexsort((full[:, 1], full[:, 0]))]
+    assert np.array_equal(np.repeat(np.arange(s.n), np.diff(frp)), full[:, 0])
+    assert np.array_equal(fcol, full[:, 1])
+    F1, E1, W1, n1 = oracle.forces(s.pos, s.box, 1, 1, s.rc, rp, col, trunc=trunc)
+    F2, E2, W2, n2 = oracle.forces_full(s.pos, s.box, 1, 1, s.rc, frp, fcol, trunc=trunc)
+    assert n2 == n1
+    np.testing.assert_allclose(F2, F1, rtol=0, atol=1e-13 * np.abs(F1).max())
+    assert E2 == pytest.approx(E1, rel=1e-13)
+    assert W2 == pytest.approx(W1, rel=1e-13)
+
+
+def test_full_list_forces_do_not_depend_on_threads(oracle):
+    s = synth.small_fcc(8, 1.0, 0.2, 17)
+    rp, col = oracle.cell_pairs(s.pos, s.box, s.rc + s.skin)
+    frp, fcol = oracle.full_pairs(rp, col)
+    was = oracle.set_threads(0)
+    try:
+        outs = []
+        for t in (1, 3, 8):
+            oracle.set_threads(t)
+            outs.append(oracle.forces_full(s.pos, s.box, 1, 1, s.rc, frp, fcol))
+    finally:
+        oracle.set_threads(was)
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0])
+        assert o[1] == outs[0][1] and o[2] == outs[0][2] and o[3] == outs[0][3]
+
+
+@pytest.mark.parametrize("name", ["lj4k", "disordered"])
+def test_sample_rows_and_virial_match_the_lists(oracle, name):
+    maker = {c[0]: c[1] for c in CASES}[name]
+    s = maker()
+    rs = s.rc + s.skin
+    rp, col = oracle.cell_pairs(s.pos, s.box, rs)
+    frp, fcol = oracle.full_pairs(rp, col)
+    idx = np.arange(s.n)
+    f, e, w, nrs, rows = oracle.sample(s.pos, s.box, 1, 1, s.rc, rs, idx, rowcap=256)
+    assert np.array_equal(nrs, np.diff(frp))
+    for i in range(s.n):
+        assert np.array_equal(rows[i, :nrs[i]], fcol[frp[i]:frp[i + 1]])
+        assert np.all(rows[i, nrs[i]:] == -1)
+    F, E, W, _ = oracle.forces(s.pos, s.box, 1, 1, s.rc, rp, col)
+    np.testing.assert_allclose(f, F, rtol=0, atol=1e-12 * np.abs(F).max())
+    assert math.fsum(e.tolist()) == pytest.approx(E, rel=1e-13)
+    assert math.fsum(w.tolist()) == pytest.approx(W, rel=1e-13)
+    # a sample is the same subset of rows on any thread count
+    was = oracle.set_threads(0)
+    try:
+        oracle.set_threads(1)
+        g = oracle.sample(s.pos, s.box, 1, 1, s.rc, rs, idx[::7], rowcap=256)
+    finally:
+        oracle.set_threads(was)
+    assert np.array_equal(g[0], f[::7]) and np.array_equal(g[4], rows[::7])
+
+
+# ---------------------------------------------------------------------------
+# Displacement-triggered rebuild (Sec. III.B).  A hot, dilute system whose
+# fastest atoms cross skin/2 within a few steps: at every step the pairs the
+# oracle's force loop counts inside rc must be exactly those of a fresh
+# brute-force search, and the list must be rebuilt at exactly the steps where
+# the largest displacement since the previous build, measured from the
+# positions themselves, first exceeds skin/2.
+# ---------------------------------------------------------------------------
+def hot_system():
+    return synth.small_fcc(6, 0.8, 0.05, 41, rc=2.5, T=4.0)
+
+
+def nve_prefix_states(oracle, s, nsteps, every, dt=0.005):
+    """Positions after k = 0..nsteps steps (each a run of its own from the
+    start: the trajectory does not depend on where a run stops)."""
+    out = [s.pos.copy()]
+    for k in range(1, nsteps + 1):
+        p, _, _, _ = oracle.nve(s.pos, s.vel, s.box, 1, 1, s.rc, s.skin, dt, k, every)
+        out.append(p)
+    return out
+
+
+def brute_interacting(oracle, pos, box, rc):
+    rp, _ = oracle.brute_pairs(pos, box, rc)
+    return int(rp[-1])
+
+
+def test_nve_trigger_keeps_every_pair(oracle):
+    s = hot_system()
+    K = 24
+    _, _, _, log = oracle.nve(s.pos, s.vel, s.box, 1, 1, s.rc, s.skin, 0.005, K, 0)
+    states = nve_prefix_states(oracle, s, K, 0)
+    L = s.box[0]
+    last_build = states[0]
+    rebuilds = 0
+    for k in range(1, K + 1):
+        assert log[k, 4] == brute_interacting(oracle, states[k], s.box, s.rc), k
+        d = states[k] - last_build
+        d -= L * np.round(d / L)
+        dmax = np.sqrt((d * d).sum(axis=1)).max()
+        if dmax > 0.5 * s.skin + 1e-9:
+            assert log[k, 5] == 1.0, k
+        elif dmax < 0.5 * s.skin - 1e-9:
+            assert log[k, 5] == 0.0, k
+        if log[k, 5] == 1.0:
+            last_build = states[k]
+            rebuilds += 1
+            assert log[k, 3] == 0.0
+        else:
+            assert log[k, 3] == pytest.approx(dmax, abs=1e-9)
+    assert rebuilds >= 3
+
+
+def test_nve_fixed_cadence_goes_stale_on_the_hot_system(oracle):
+    # The same system with a rebuild every 10 steps misses pairs: the contrast
+    # that shows the trigger pin can fail.
+    s = hot_system()
+    K = 20
+    _, _, _, log = oracle.nve(s.pos, s.vel, s.box, 1, 1, s.rc, s.skin, 0.005, K, 10)
+    states = nve_prefix_states(oracle, s, K, 10)
+    missing = [k for k in range(1, K + 1)
+               if log[k, 4] < brute_interacting(oracle, states[k], s.box, s.rc)]
+    assert missing
+    assert np.all(log[::10, 5] == 1.0) and np.all(log[1:10, 5] == 0.0)
+    assert log[:, 3].max() > 0.5 * s.skin
