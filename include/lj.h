@@ -27,10 +27,13 @@
  *     them.  Host pointers are ordinary host memory.
  *   - Positions: `pos` with `layout`
  *       LJ_AOS4: n x 4 doubles, record i = (x_i, y_i, z_i, pad), 32-byte aligned;
- *       LJ_SOA : 3 x n doubles, x block then y block then z block.
+ *       LJ_SOA : 3 x n doubles, x block then y block then z block;
+ *       LJ_AOS8: n x 8 doubles, record i = (x_i, y_i, z_i, pad, 4 doubles of the
+ *                caller), 32-byte aligned, n <= 2^26.
  *     Coordinates must be finite and lie in [0, box[d]).
  *   - Forces are returned in the same layout as the positions (the pad of
- *     an LJ_AOS4 record is written as 0).
+ *     an LJ_AOS4 record is written as 0; LJ_AOS8 positions give LJ_AOS4
+ *     forces).
  *   - box: host array of 3 box lengths of the periodic, orthorhombic box.
  *     Every box[d] must be >= 2 (rc + skin) so that the nearest image of a
  *     pair within the search length is unique (LJ_E_BOX otherwise).
@@ -42,6 +45,10 @@
  *   - Work is enqueued on the context's HIP stream and is asynchronous unless
  *     a call says otherwise.  A context must be used by one host thread at a
  *     time; two calls that overlap on one context race.
+ *   - Errors found on the device (a bad coordinate, a list row over its
+ *     capacity) are recorded in the context and reported by the next lj_sync.
+ *     Until then every force and integrator launch of the context leaves its
+ *     outputs untouched.
  */
 #ifndef LJ_H
 #define LJ_H
@@ -94,6 +101,17 @@ typedef enum {
 /* position / force layouts */
 #define LJ_AOS4 0
 #define LJ_SOA 1
+#define LJ_AOS8 2        /* positions only: n records of 8 doubles (x, y, z, pad, u0, u1, u2,
+                            pad), 32-byte aligned, of which the library reads the first
+                            three: the packed (q, p) records of Sec. V.F (in the integrator
+                            the second half holds the velocity).  Forces for LJ_AOS8
+                            positions are LJ_AOS4 records.  At most 2^26 atoms */
+/* truncation of the potential at rc (Sec. III.A) */
+#define LJ_TRUNC_SHIFT 0         /* V(r) - V(rc) for r < rc: the potential is shifted by a
+                                    constant; the force is that of V and jumps to 0 at rc */
+#define LJ_TRUNC_FORCE_SHIFT 1   /* V(r) - V(rc) + (r - rc) Fc, Fc = -V'(rc): force
+                                    F(r) - Fc along the pair; force and energy both vanish
+                                    at rc (the remedy for energy conservation) */
 
 typedef struct lj_ctx lj_ctx;
 typedef struct lj_cells lj_cells;
@@ -126,8 +144,10 @@ LJ_API lj_status lj_destroy(lj_ctx* ctx);
 /* Point the context at another stream (not owned). */
 LJ_API lj_status lj_set_stream(lj_ctx* ctx, void* stream);
 /* Wait for the context's stream and report device-side errors raised by
- * asynchronous calls since the last check (LJ_E_POSITION, LJ_E_CAPACITY);
- * each error is reported once. */
+ * asynchronous calls since the last check (LJ_E_POSITION, LJ_E_CAPACITY, and
+ * LJ_E_STALE for an integrator step at a fixed rebuild cadence whose atoms
+ * had moved more than skin/2 since the list was built); each error is
+ * reported once and cleared. */
 LJ_API lj_status lj_sync(lj_ctx* ctx);
 
 /* ------------------------------------------------------------------ cells */
@@ -217,12 +237,15 @@ LJ_API lj_status lj_list_device_view(const lj_list* list, lj_list_view* out);
  * NULL.  precision: LJ_FP64 or LJ_MIXED.  The list must have been built for
  * the same n, layout, box and rc (LJ_E_STALE otherwise), and is valid while
  * no atom has moved more than skin/2 since the build (not checked here).
+ * trunc: LJ_TRUNC_SHIFT (the above) or LJ_TRUNC_FORCE_SHIFT (fs - Fc / r in
+ * place of fs, and (r - rc) Fc added to each pair's energy).
  * Asynchronous; energy, virial and npairs are reduced on the device in a
- * fixed order, so a full list gives bitwise-reproducible results. */
+ * fixed order, so a full list gives bitwise-reproducible results.  While an
+ * error is pending on the context (see lj_sync) nothing is written. */
 LJ_API lj_status lj_forces(lj_ctx* ctx, const double* pos, int64_t n, int32_t layout,
                     const double box[3], double eps, double sigma, double rc,
-                    const lj_list* list, int32_t precision, double* force, double* energy,
-                    double* virial, int64_t* npairs);
+                    const lj_list* list, int32_t precision, int32_t trunc, double* force,
+                    double* energy, double* virial, int64_t* npairs);
 
 /* ----------------------------------------------------------------- batches */
 
@@ -242,8 +265,9 @@ LJ_API lj_status lj_build_neighbors_batch(lj_ctx* ctx, const double* pos, int32_
  * npairs: device array of nsys int64 or NULL. */
 LJ_API lj_status lj_forces_batch(lj_ctx* ctx, const double* pos, int32_t layout,
                                  const lj_list* list, const double* eps, const double* sigma,
-                                 const double* rc, int32_t precision, double* force,
-                                 double* energy, double* virial, int64_t* npairs);
+                                 const double* rc, int32_t precision, int32_t trunc,
+                                 double* force, double* energy, double* virial,
+                                 int64_t* npairs);
 /* Row statistics of system s of a list (synchronous). */
 LJ_API lj_status lj_list_sys_info(const lj_list* list, int32_t s, int64_t* n, int32_t* max_row,
                                   int64_t* entries, int32_t* cap);
@@ -253,45 +277,68 @@ LJ_API lj_status lj_list_sys_info(const lj_list* list, int32_t s, int64_t* n, in
 /* Velocity-Verlet NVE integration at unit mass around the force path.  One
  * step, as in the oracle:
  *   v += F dt/2;  x += v dt, wrapped to x - L floor(x/L) (a result equal to L
- *   becomes 0);  if step % rebuild_every == 0 the list is rebuilt in place at
- *   the new positions (lj_update_neighbors);  F = F(x) (lj_forces, in the
- *   integrator's precision);  v += F dt/2.
+ *   becomes 0), and each atom's displacement since the last list build grows
+ *   by v dt;  the list is rebuilt in place at the new positions
+ *   (lj_update_neighbors)
+ *     rebuild_every > 0: when step % rebuild_every == 0 (a fixed cadence; a
+ *       step between builds at which some atom has moved more than skin/2
+ *       since the build is reported as LJ_E_STALE by lj_sync, the list may
+ *       then miss pairs);
+ *     rebuild_every = 0: when some atom's displacement since the last build
+ *       exceeds skin/2 (|d|^2 = (dx*dx + dy*dy) + dz*dz > (skin/2)^2), the
+ *       first step at which a pair beyond rs at the build could have come
+ *       within rc (Sec. III.B: the list stays exact); decided on the device;
+ *   F = F(x) (lj_forces, in the integrator's precision and truncation);
+ *   v += F dt/2.
+ * With a full list and a fixed cadence, the kick that ends a step is folded
+ * into the force pass (the momentum update of Alg. 1), and inside a rebuild
+ * cycle so is the kick that opens the next step, each rounded as a separate
+ * kick (the trajectory is the same bit for bit).
  * All state stays on the device and the integrator itself is FP64 whatever
  * the force precision.  The caller's arrays are bound at creation (so that a
  * captured HIP graph can replay them): pos, vel and force are device arrays
- * of n records in `layout`; log is a device array of log_rows x 5 doubles
- * that receives, for step s (row s, when s < log_rows): potential energy,
- * kinetic energy (sum of v^2/2), virial, the largest displacement of any atom
- * since the last list build, and the number of interacting pairs.  The list
- * must belong to the same context and stay alive while the integrator is
- * used.  *out is owned by the library until lj_nve_free. */
+ * of n records in `layout`; with LJ_AOS8, pos holds the packed (x, y, z, pad,
+ * vx, vy, vz, pad) records, vel must be pos + 4 and force is LJ_AOS4.  log
+ * is a device array of log_rows x 6 doubles that receives, for step s (row s,
+ * when s < log_rows): potential energy, kinetic energy (sum of v^2/2),
+ * virial, the largest displacement of any atom since the last list build
+ * (0 at a step that rebuilt), the number of interacting pairs, and 1 if the
+ * list was rebuilt at that step (row 0: 1).  The list must belong to the same
+ * context and stay alive while the integrator is used.  *out is owned by the
+ * library until lj_nve_free. */
 typedef struct lj_nve lj_nve;
 LJ_API lj_status lj_nve_create(lj_ctx* ctx, double* pos, double* vel, double* force, int64_t n,
                                int32_t layout, const double box[3], double eps, double sigma,
-                               double rc, int32_t precision, lj_list* list, double dt,
-                               int32_t rebuild_every, double* log, int64_t log_rows,
+                               double rc, int32_t precision, int32_t trunc, lj_list* list,
+                               double dt, int32_t rebuild_every, double* log, int64_t log_rows,
                                lj_nve** out);
 /* The integrator of a batch list: eps, sigma, rc are host arrays of nsys
- * values; the log holds log_rows x nsys x 5 doubles (row, system, quantity). */
+ * values; the log holds log_rows x nsys x 6 doubles (row, system, quantity).
+ * With rebuild_every = 0 every system is rebuilt at a step at which any
+ * system needs it. */
 LJ_API lj_status lj_nve_create_batch(lj_ctx* ctx, double* pos, double* vel, double* force,
                                      int32_t layout, const double* eps, const double* sigma,
-                                     const double* rc, int32_t precision, lj_list* list,
-                                     double dt, int32_t rebuild_every, double* log,
-                                     int64_t log_rows, lj_nve** out);
+                                     const double* rc, int32_t precision, int32_t trunc,
+                                     lj_list* list, double dt, int32_t rebuild_every,
+                                     double* log, int64_t log_rows, lj_nve** out);
 /* Step 0: forces at the current positions and log row 0; resets the step
  * count and the displacement record.  Asynchronous. */
 LJ_API lj_status lj_nve_init(lj_nve* nve);
 /* Advance nsteps steps.  use_graph != 0: whole rebuild cycles (rebuild_every
- * steps ending with a rebuild) are captured once into a HIP graph and
- * replayed; the remaining steps run as ordinary launches.  Within a run the
- * kick that ends a step and the drift that opens the next are one pass over
- * the atoms; the arithmetic is the same as taking the steps one call at a
+ * steps ending with a rebuild; 10 steps when rebuild_every = 0) are captured
+ * once into a HIP graph and replayed; the remaining steps run as ordinary
+ * launches.  The arithmetic is the same as taking the steps one call at a
  * time, bit for bit, and vel holds the synchronised velocities when the run
  * ends.  Requires the context's stream to be a created stream (not the null
- * stream) when use_graph != 0.  Asynchronous; list overflow and bad
- * coordinates are reported by lj_sync. */
+ * stream) when use_graph != 0.  Asynchronous.  If a list rebuild meets a bad
+ * coordinate or a row over the list's capacity, the run stops at its last
+ * good step: pos, vel and force are restored to that step's values, the
+ * later steps (and their log rows) are skipped, lj_sync reports the error
+ * and lj_nve_steps the last good step.  The list must then be built again
+ * (lj_build_neighbors) for a new integrator. */
 LJ_API lj_status lj_nve_run(lj_nve* nve, int32_t nsteps, int32_t use_graph);
-/* Steps taken since lj_nve_init (host counter). */
+/* Steps completed since lj_nve_init.  Synchronous (reads the device's step
+ * counter: after an error, the last good step). */
 LJ_API lj_status lj_nve_steps(const lj_nve* nve, int64_t* steps);
 LJ_API lj_status lj_nve_free(lj_nve* nve);
 
@@ -310,7 +357,11 @@ LJ_API lj_status lj_nve_free(lj_nve* nve);
 #define LJ_TUNE_CELL_DIV 2      /* lists built without caller cells use cells of side
                                    (rc + skin) / k in y and z and half that in x,
                                    k = 1, 2, 3 or 4; default 2 */
-#define LJ_TUNE_N 3
+#define LJ_TUNE_KICK 3          /* integrators created afterwards: 1 folds the kicks into
+                                   the force pass where it can (full list, fixed cadence;
+                                   the default), 2 keeps them in separate kernels.  The
+                                   trajectory is the same bit for bit */
+#define LJ_TUNE_N 4
 /* Set knob `knob` to `value` (LJ_E_INVALID for an unknown knob or value). */
 LJ_API lj_status lj_tune_set(lj_ctx* ctx, int32_t knob, int32_t value);
 /* Current value of a knob (0 = default). */

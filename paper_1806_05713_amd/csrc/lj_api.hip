@@ -112,9 +112,12 @@ lj_status check_common(lj_ctx* ctx, const double* pos, int64_t n, int32_t layout
     if (n < 1) return lj_fail(LJ_E_INVALID, "n must be >= 1");
     if (n > LJ_MAX_ATOMS)
         return lj_fail(LJ_E_INVALID, "n exceeds LJ_MAX_ATOMS (2^27 atoms per call)");
-    if (layout != LJ_AOS4 && layout != LJ_SOA) return lj_fail(LJ_E_INVALID, "unknown layout");
-    if (layout == LJ_AOS4 && ((uintptr_t)pos & 31u))
-        return lj_fail(LJ_E_INVALID, "LJ_AOS4 positions must be 32-byte aligned");
+    if (layout != LJ_AOS4 && layout != LJ_SOA && layout != LJ_AOS8)
+        return lj_fail(LJ_E_INVALID, "unknown layout");
+    if (layout != LJ_SOA && ((uintptr_t)pos & 31u))
+        return lj_fail(LJ_E_INVALID, "AoS positions must be 32-byte aligned");
+    if (layout == LJ_AOS8 && n > LJ_MAX_ATOMS / 2)
+        return lj_fail(LJ_E_INVALID, "LJ_AOS8 holds at most 2^26 atoms per call");
     return LJ_OK;
 }
 
@@ -371,6 +374,7 @@ lj_status build_list(lj_ctx* ctx, const double* pos, int32_t layout, int nsys, c
     l->lanes = lanes;
     l->build_lanes = lj_build_lanes(ctx, lanes);
     l->device = ctx->device;
+    l->stream = ctx->stream;
     l->fc_valid = false;
     lj_status st;
     const lj_cells* c = cells;
@@ -463,16 +467,29 @@ lj_status build_list(lj_ctx* ctx, const double* pos, int32_t layout, int nsys, c
 
 // Force constants for the list's systems; uploaded when they change.
 lj_status set_fconst(lj_ctx* ctx, lj_list* l, const double* eps, const double* sigma,
-                     const double* rc) {
+                     const double* rc, int trunc) {
     std::vector<lj_fconst> f((size_t)l->nsys);
     for (int s = 0; s < l->nsys; ++s)
-        f[(size_t)s] = lj_make_fconst(eps[s], sigma[s], rc[s], l->hsys[(size_t)s].box);
+        f[(size_t)s] = lj_make_fconst(eps[s], sigma[s], rc[s], l->hsys[(size_t)s].box, trunc);
     if (l->fc_valid && memcmp(f.data(), l->hfc.data(), f.size() * sizeof(lj_fconst)) == 0)
         return LJ_OK;
     l->hfc = f;
     lj_status st = upload(l->fc, l->hfc.data(), l->nsys, ctx->stream);
     if (st) return st;
     l->fc_valid = true;
+    return LJ_OK;
+}
+
+lj_status check_trunc(int32_t trunc) {
+    if (trunc != LJ_TRUNC_SHIFT && trunc != LJ_TRUNC_FORCE_SHIFT)
+        return lj_fail(LJ_E_INVALID, "unknown truncation");
+    return LJ_OK;
+}
+
+// Forces are written as 32-byte records for AoS positions of either stride.
+lj_status check_force_out(int32_t layout, const double* force) {
+    if (layout != LJ_SOA && ((uintptr_t)force & 31u))
+        return lj_fail(LJ_E_INVALID, "AoS forces must be 32-byte aligned");
     return LJ_OK;
 }
 
@@ -562,7 +579,13 @@ extern "C" lj_status lj_sync(lj_ctx* ctx) {
     if (h.flags & LJ_DEV_BAD_POSITION)
         return lj_fail(LJ_E_POSITION, "a coordinate is non-finite or outside [0, box)");
     if (h.flags & LJ_DEV_ROW_OVERFLOW)
-        return lj_fail(LJ_E_CAPACITY, "a list row exceeded its capacity");
+        return lj_fail(LJ_E_CAPACITY, (h.flags & LJ_DEV_RESTORED)
+                                          ? "a list row exceeded its capacity (the integrator "
+                                            "stopped at its last good step)"
+                                          : "a list row exceeded its capacity");
+    if (h.flags & LJ_DEV_STALE)
+        return lj_fail(LJ_E_STALE, "an integrator step at a fixed rebuild cadence found an atom "
+                                   "moved more than skin/2 since the list was built");
     return LJ_OK;
 }
 
@@ -718,24 +741,23 @@ extern "C" lj_status lj_update_neighbors(lj_ctx* ctx, const double* pos, int64_t
     }
     DeviceGuard guard(ctx->device);
     if ((st = lj_list_ensure_cells(ctx, l))) return st;   // lists built on caller cells
+    l->stream = ctx->stream;
     if ((st = lj_launch_cells(ctx, pos, layout, l->cells))) return st;
     return lj_launch_neighbors(ctx, l->cells, l, false);
 }
 
 // Statistics of the list's latest build, summed on the device first if the
-// build did not do it.  The list may have been rebuilt on any stream of its
-// context: wait for the whole device.
+// build did not do it; ordered on the stream of the list's latest build.
 lj_status read_list_stats(const lj_list* cl, lj_list_stats* out) {
     lj_list* l = const_cast<lj_list*>(cl);
     DeviceGuard guard(l->device);
-    LJ_HIP(hipDeviceSynchronize());
     if (l->stats_stale) {
-        lj_status st = lj_launch_list_stats(nullptr, l);
+        lj_status st = lj_launch_list_stats(l->stream, l);
         if (st) return st;
-        LJ_HIP(hipDeviceSynchronize());
     }
-    LJ_HIP(hipMemcpy(out, l->stats, (size_t)l->nsys * sizeof(lj_list_stats),
-                     hipMemcpyDeviceToHost));
+    LJ_HIP(hipMemcpyAsync(out, l->stats, (size_t)l->nsys * sizeof(lj_list_stats),
+                          hipMemcpyDeviceToHost, l->stream));
+    LJ_HIP(hipStreamSynchronize(l->stream));
     return LJ_OK;
 }
 
@@ -843,14 +865,13 @@ extern "C" lj_status lj_list_free(lj_list* l) {
 
 extern "C" lj_status lj_forces(lj_ctx* ctx, const double* pos, int64_t n, int32_t layout,
                                const double box[3], double eps, double sigma, double rc,
-                               const lj_list* list, int32_t precision, double* force,
-                               double* energy, double* virial, int64_t* npairs) {
+                               const lj_list* list, int32_t precision, int32_t trunc,
+                               double* force, double* energy, double* virial, int64_t* npairs) {
     lj_status st = check_common(ctx, pos, n, layout);
     if (st) return st;
     if (!list || !force || !energy || !virial)
         return lj_fail(LJ_E_INVALID, "list, force, energy or virial is NULL");
-    if (layout == LJ_AOS4 && ((uintptr_t)force & 31u))
-        return lj_fail(LJ_E_INVALID, "LJ_AOS4 forces must be 32-byte aligned");
+    if ((st = check_force_out(layout, force)) || (st = check_trunc(trunc))) return st;
     if (precision != LJ_FP64 && precision != LJ_MIXED)
         return lj_fail(LJ_E_INVALID, "unknown precision");
     if (!box) return lj_fail(LJ_E_INVALID, "box is NULL");
@@ -861,80 +882,90 @@ extern "C" lj_status lj_forces(lj_ctx* ctx, const double* pos, int64_t n, int32_
     if ((st = check_params(1, &eps, &sigma, &rc, list))) return st;
     DeviceGuard guard(ctx->device);
     lj_list* l = const_cast<lj_list*>(list);
-    if ((st = set_fconst(ctx, l, &eps, &sigma, &rc))) return st;
+    if ((st = set_fconst(ctx, l, &eps, &sigma, &rc, trunc))) return st;
     if (precision == LJ_MIXED && (st = lj_list_ensure_q32(l))) return st;
-    return lj_launch_forces(ctx, pos, layout, precision, l, l->fc, force, energy, virial, npairs);
+    lj_force_opts o;
+    o.trunc = trunc;
+    return lj_launch_forces(ctx, pos, layout, precision, l, l->fc, force, energy, virial, npairs,
+                            o);
 }
 
 extern "C" lj_status lj_forces_batch(lj_ctx* ctx, const double* pos, int32_t layout,
                                      const lj_list* list, const double* eps, const double* sigma,
-                                     const double* rc, int32_t precision, double* force,
-                                     double* energy, double* virial, int64_t* npairs) {
+                                     const double* rc, int32_t precision, int32_t trunc,
+                                     double* force, double* energy, double* virial,
+                                     int64_t* npairs) {
     if (!list || !eps || !sigma || !rc || !force || !energy || !virial)
         return lj_fail(LJ_E_INVALID, "NULL argument");
     lj_status st = check_common(ctx, pos, list->n, layout);
     if (st) return st;
-    if (layout == LJ_AOS4 && ((uintptr_t)force & 31u))
-        return lj_fail(LJ_E_INVALID, "LJ_AOS4 forces must be 32-byte aligned");
+    if ((st = check_force_out(layout, force)) || (st = check_trunc(trunc))) return st;
     if (precision != LJ_FP64 && precision != LJ_MIXED)
         return lj_fail(LJ_E_INVALID, "unknown precision");
     if ((st = check_params(list->nsys, eps, sigma, rc, list))) return st;
     DeviceGuard guard(ctx->device);
     lj_list* l = const_cast<lj_list*>(list);
-    if ((st = set_fconst(ctx, l, eps, sigma, rc))) return st;
+    if ((st = set_fconst(ctx, l, eps, sigma, rc, trunc))) return st;
     if (precision == LJ_MIXED && (st = lj_list_ensure_q32(l))) return st;
-    return lj_launch_forces(ctx, pos, layout, precision, l, l->fc, force, energy, virial, npairs);
+    lj_force_opts o;
+    o.trunc = trunc;
+    return lj_launch_forces(ctx, pos, layout, precision, l, l->fc, force, energy, virial, npairs,
+                            o);
 }
 
 // -------------------------------------------------------------- integrator
 
 static lj_status nve_create(lj_ctx* ctx, double* pos, double* vel, double* force, int32_t layout,
                             const double* eps, const double* sigma, const double* rc,
-                            int32_t precision, lj_list* list, double dt, int32_t rebuild_every,
-                            double* log, int64_t log_rows, lj_nve** out) {
+                            int32_t precision, int32_t trunc, lj_list* list, double dt,
+                            int32_t rebuild_every, double* log, int64_t log_rows, lj_nve** out) {
     lj_status st = check_common(ctx, pos, list ? list->n : 0, layout);
     if (st) return st;
     if (!vel || !force || !list || !out)
         return lj_fail(LJ_E_INVALID, "vel, force, list or out is NULL");
-    if (layout == LJ_AOS4 && (((uintptr_t)vel & 31u) || ((uintptr_t)force & 31u)))
-        return lj_fail(LJ_E_INVALID, "LJ_AOS4 arrays must be 32-byte aligned");
+    if (layout == LJ_AOS4 && ((uintptr_t)vel & 31u))
+        return lj_fail(LJ_E_INVALID, "LJ_AOS4 velocities must be 32-byte aligned");
+    if (layout == LJ_AOS8 && vel != pos + 4)
+        return lj_fail(LJ_E_INVALID, "with LJ_AOS8 records vel must be pos + 4");
+    if ((st = check_force_out(layout, force)) || (st = check_trunc(trunc))) return st;
     if (!finite_pos(dt)) return lj_fail(LJ_E_INVALID, "dt must be finite and > 0");
     if (precision != LJ_FP64 && precision != LJ_MIXED)
         return lj_fail(LJ_E_INVALID, "unknown precision");
-    if (rebuild_every < 1) return lj_fail(LJ_E_INVALID, "rebuild_every must be >= 1");
+    if (rebuild_every < 0) return lj_fail(LJ_E_INVALID, "rebuild_every must be >= 0");
     if (log_rows < 0 || (log_rows > 0 && !log)) return lj_fail(LJ_E_INVALID, "log is NULL");
     if ((st = check_params(list->nsys, eps, sigma, rc, list))) return st;
     DeviceGuard guard(ctx->device);
     if ((st = lj_list_ensure_cells(ctx, list))) return st;
     if (precision == LJ_MIXED && (st = lj_list_ensure_q32(list))) return st;
+    list->stream = ctx->stream;   // the integrator rebuilds it there
     std::vector<lj_fconst> f((size_t)list->nsys);
     for (int s = 0; s < list->nsys; ++s)
-        f[(size_t)s] = lj_make_fconst(eps[s], sigma[s], rc[s], list->hsys[(size_t)s].box);
-    return lj_nve_make(ctx, pos, vel, force, layout, f.data(), precision, list, dt, rebuild_every,
-                       log, log_rows, out);
+        f[(size_t)s] = lj_make_fconst(eps[s], sigma[s], rc[s], list->hsys[(size_t)s].box, trunc);
+    return lj_nve_make(ctx, pos, vel, force, layout, f.data(), precision, trunc, list, dt,
+                       rebuild_every, log, log_rows, out);
 }
 
 extern "C" lj_status lj_nve_create(lj_ctx* ctx, double* pos, double* vel, double* force,
                                    int64_t n, int32_t layout, const double box[3], double eps,
-                                   double sigma, double rc, int32_t precision, lj_list* list,
-                                   double dt, int32_t rebuild_every, double* log,
+                                   double sigma, double rc, int32_t precision, int32_t trunc,
+                                   lj_list* list, double dt, int32_t rebuild_every, double* log,
                                    int64_t log_rows, lj_nve** out) {
     if (!list || !box) return lj_fail(LJ_E_INVALID, "list or box is NULL");
     if (list->nsys != 1) return lj_fail(LJ_E_INVALID, "a batch list needs lj_nve_create_batch");
     if (list->n != n) return lj_fail(LJ_E_STALE, "list was built for another atom count");
     for (int d = 0; d < 3; ++d)
         if (list->hsys[0].box[d] != box[d]) return lj_fail(LJ_E_STALE, "list was built for another box");
-    return nve_create(ctx, pos, vel, force, layout, &eps, &sigma, &rc, precision, list, dt,
+    return nve_create(ctx, pos, vel, force, layout, &eps, &sigma, &rc, precision, trunc, list, dt,
                       rebuild_every, log, log_rows, out);
 }
 
 extern "C" lj_status lj_nve_create_batch(lj_ctx* ctx, double* pos, double* vel, double* force,
                                          int32_t layout, const double* eps, const double* sigma,
-                                         const double* rc, int32_t precision, lj_list* list,
-                                         double dt, int32_t rebuild_every, double* log,
-                                         int64_t log_rows, lj_nve** out) {
+                                         const double* rc, int32_t precision, int32_t trunc,
+                                         lj_list* list, double dt, int32_t rebuild_every,
+                                         double* log, int64_t log_rows, lj_nve** out) {
     if (!list || !eps || !sigma || !rc) return lj_fail(LJ_E_INVALID, "NULL argument");
-    return nve_create(ctx, pos, vel, force, layout, eps, sigma, rc, precision, list, dt,
+    return nve_create(ctx, pos, vel, force, layout, eps, sigma, rc, precision, trunc, list, dt,
                       rebuild_every, log, log_rows, out);
 }
 
@@ -951,8 +982,7 @@ extern "C" lj_status lj_nve_run(lj_nve* nve, int32_t nsteps, int32_t use_graph) 
 
 extern "C" lj_status lj_nve_steps(const lj_nve* nve, int64_t* steps) {
     if (!nve || !steps) return lj_fail(LJ_E_INVALID, "integrator or steps is NULL");
-    *steps = lj_nve_step_count(nve);
-    return LJ_OK;
+    return lj_nve_device_steps(const_cast<lj_nve*>(nve), steps);
 }
 
 extern "C" lj_status lj_nve_free(lj_nve* nve) {
@@ -971,6 +1001,7 @@ extern "C" lj_status lj_tune_set(lj_ctx* ctx, int32_t knob, int32_t value) {
             break;
         case LJ_TUNE_FORCE_BATCH: ok = value == 0 || value == 2 || value == 4 || value == 8; break;
         case LJ_TUNE_CELL_DIV: ok = value >= 0 && value <= 4; break;
+        case LJ_TUNE_KICK: ok = value >= 0 && value <= 2; break;
         default: return lj_fail(LJ_E_INVALID, "unknown tuning knob");
     }
     if (!ok) return lj_fail(LJ_E_INVALID, "value not allowed for this knob");

@@ -22,10 +22,17 @@ __global__ void k_zero(uint32_t* __restrict__ p, int64_t words) {
     for (; i < words; i += stride) p[i] = 0u;
 }
 
+// When `gate` is not NULL a kernel does nothing unless *gate != 0 (a rebuild
+// decided on the device).
+__device__ __forceinline__ bool gated_off(const int32_t* gate) {
+    return gate && __builtin_nontemporal_load(gate) == 0;
+}
+
+// Position of atom i: AoS records of 32 (LJ_AOS4) or 64 (LJ_AOS8) bytes, or SoA.
 __device__ __forceinline__ void load_xyz(const double* __restrict__ pos, int64_t n, int layout,
                                          int64_t i, double& x, double& y, double& z) {
-    if (layout == LJ_AOS4) {
-        const double4 q = reinterpret_cast<const double4*>(pos)[i];
+    if (layout != LJ_SOA) {
+        const double4 q = reinterpret_cast<const double4*>(pos)[layout == LJ_AOS8 ? 2 * i : i];
         x = q.x;
         y = q.y;
         z = q.z;
@@ -46,9 +53,11 @@ struct BinArgs {
     int32_t* slot;
     int32_t* count;
     lj_dev_status* st;
+    const int32_t* gate;
 };
 
 __global__ __launch_bounds__(LJ_BLOCK) void k_bin(BinArgs a) {
+    if (gated_off(a.gate)) return;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     const lj_sys& sy = a.sys[a.atom_sys ? a.atom_sys[i] : 0];
@@ -73,7 +82,9 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_bin(BinArgs a) {
 __global__ __launch_bounds__(LJ_BLOCK) void k_place(int64_t n, const int32_t* __restrict__ cid,
                                                     const int32_t* __restrict__ slot,
                                                     const int32_t* __restrict__ cell_start,
-                                                    int32_t* __restrict__ order_tmp) {
+                                                    int32_t* __restrict__ order_tmp,
+                                                    const int32_t* gate) {
+    if (gated_off(gate)) return;
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
     order_tmp[cell_start[cid[i]] + slot[i]] = (int32_t)i;
@@ -88,7 +99,9 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_rank(int64_t n, const int32_t* __r
                                                    const double* __restrict__ pos, int layout,
                                                    int32_t* __restrict__ order,
                                                    double4* __restrict__ spos,
-                                                   float4* __restrict__ spos32) {
+                                                   float4* __restrict__ spos32,
+                                                   const int32_t* gate) {
+    if (gated_off(gate)) return;
     const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int v = order_tmp[p];
@@ -160,7 +173,9 @@ __device__ __forceinline__ int4 load4(const int32_t* __restrict__ in, int64_t i4
 
 __global__ __launch_bounds__(LJ_BLOCK) void k_scan_reduce(const int32_t* __restrict__ in,
                                                           int64_t m,
-                                                          int32_t* __restrict__ tile_sums) {
+                                                          int32_t* __restrict__ tile_sums,
+                                                          const int32_t* gate) {
+    if (gated_off(gate)) return;
     __shared__ int lds[LJ_WAVES_PER_BLOCK];
     const int4 v = load4(in, blockIdx.x * (int64_t)LJ_BLOCK + threadIdx.x, m);
     const int s = block_sum(v.x + v.y + v.z + v.w, lds);
@@ -170,7 +185,8 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_scan_reduce(const int32_t* __restr
 __global__ __launch_bounds__(LJ_BLOCK) void k_scan_tiles(int32_t* __restrict__ in,
                                                          int32_t* __restrict__ out, int64_t m,
                                                          const int32_t* __restrict__ tile_sums,
-                                                         int clear_in) {
+                                                         int clear_in, const int32_t* gate) {
+    if (gated_off(gate)) return;
     __shared__ int lds[LJ_WAVES_PER_BLOCK];
     // offset of this tile: the sums of the tiles before it
     int before = 0;
@@ -209,7 +225,9 @@ constexpr int64_t SCAN1_MAX = (int64_t)SCAN1_THREADS * SCAN1_PER;
 __device__ __forceinline__ int scan1_pad(int i) { return i + (i >> 5); }
 __global__ __launch_bounds__(SCAN1_THREADS) void k_scan_single(int32_t* __restrict__ in,
                                                                int32_t* __restrict__ out,
-                                                               int64_t m, int clear_in) {
+                                                               int64_t m, int clear_in,
+                                                               const int32_t* gate) {
+    if (gated_off(gate)) return;
     __shared__ int buf[SCAN1_MAX + SCAN1_MAX / 32];
     __shared__ int lds[SCAN1_THREADS / 64];
     const int t = threadIdx.x;
@@ -288,25 +306,26 @@ lj_status lj_launch_zero(hipStream_t s, void* p, int64_t bytes) {
 }
 
 lj_status lj_launch_scan(hipStream_t s, int32_t* in, int32_t* out, int64_t m, int32_t* work,
-                         bool clear_in) {
+                         bool clear_in, const int32_t* gate) {
     const int64_t nt = (m + SCAN_TILE - 1) / SCAN_TILE;
     if (nt > 16 * SCAN_TILE) return lj_fail(LJ_E_CAPACITY, "scan: more than 16.7M elements");
     if (m == 0) return lj_launch_zero(s, out, sizeof(int32_t));
     if (m <= SCAN1_MAX) {
         hipLaunchKernelGGL(k_scan_single, dim3(1), dim3(SCAN1_THREADS), 0, s, in, out, m,
-                           clear_in ? 1 : 0);
+                           clear_in ? 1 : 0, gate);
         LJ_HIP(hipGetLastError());
         return LJ_OK;
     }
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nt), dim3(LJ_BLOCK), 0, s,
-                       (const int32_t*)in, m, work);
+                       (const int32_t*)in, m, work, gate);
     hipLaunchKernelGGL(k_scan_tiles, dim3((unsigned)nt), dim3(LJ_BLOCK), 0, s, in, out, m,
-                       (const int32_t*)work, clear_in ? 1 : 0);
+                       (const int32_t*)work, clear_in ? 1 : 0, gate);
     LJ_HIP(hipGetLastError());
     return LJ_OK;
 }
 
-lj_status lj_launch_cells(lj_ctx* ctx, const double* pos, int layout, lj_cells* c) {
+lj_status lj_launch_cells(lj_ctx* ctx, const double* pos, int layout, lj_cells* c,
+                          const int32_t* gate) {
     hipStream_t s = ctx->stream;
     lj_prof_scope prof(ctx, LJ_PROF_CELLS);
     lj_status st;
@@ -326,19 +345,20 @@ lj_status lj_launch_cells(lj_ctx* ctx, const double* pos, int layout, lj_cells* 
     a.slot = c->slot;
     a.count = c->count;
     a.st = ctx->st;
+    a.gate = gate;
     hipLaunchKernelGGL(k_bin, dim3(grid_for(c->n, LJ_BLOCK)), dim3(LJ_BLOCK), 0, s, a);
     LJ_HIP(hipGetLastError());
-    st = lj_launch_scan(s, c->count, c->cell_start, c->ncell, c->block_sums, true);
+    st = lj_launch_scan(s, c->count, c->cell_start, c->ncell, c->block_sums, true, gate);
     if (st) return st;
     c->counts_dirty = false;
     hipLaunchKernelGGL(k_place, dim3(grid_for(c->n, LJ_BLOCK)), dim3(LJ_BLOCK), 0, s, c->n,
                        (const int32_t*)c->cid, (const int32_t*)c->slot,
-                       (const int32_t*)c->cell_start, c->order_tmp);
+                       (const int32_t*)c->cell_start, c->order_tmp, gate);
     LJ_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_rank, dim3(grid_for(c->n, LJ_BLOCK)), dim3(LJ_BLOCK), 0, s, c->n,
                        (const int32_t*)c->cid, (const int32_t*)c->cell_start,
                        (const int32_t*)c->order_tmp, pos, layout, c->order, c->spos,
-                       c->spos32);
+                       c->spos32, gate);
     LJ_HIP(hipGetLastError());
     return LJ_OK;
 }

@@ -38,43 +38,51 @@ namespace {
 
 using namespace ljf;
 
-// Block partials (E, W, count) -> partials[4 * block], summed in a fixed
-// order.  No atomics: a device-scope atomic must stay coherent across the
-// eight per-XCD L2 caches and is resolved beyond them, so thousands of blocks
-// hitting one counter serialise.
-__device__ void block_partials(const ForceArgs& a, int64_t blk, double e, double w, double cnt) {
-    __shared__ double red[LJ_WAVES_PER_BLOCK][3];
+// Block partials (E, W, count, kinetic energy) -> partials[4 * block],
+// summed in a fixed order.  No atomics: a device-scope atomic must stay
+// coherent across the eight per-XCD L2 caches and is resolved beyond them, so
+// thousands of blocks hitting one counter serialise.
+__device__ void block_partials(const ForceArgs& a, int64_t blk, double e, double w, double cnt,
+                               double ke) {
+    __shared__ double red[LJ_WAVES_PER_BLOCK][4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     e = wave_sum(e);
     w = wave_sum(w);
     cnt = wave_sum(cnt);
+    ke = wave_sum(ke);
     if (lane == 0) {
         red[wave][0] = e;
         red[wave][1] = w;
         red[wave][2] = cnt;
+        red[wave][3] = ke;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double be = 0.0, bw = 0.0, bc = 0.0;
+        double be = 0.0, bw = 0.0, bc = 0.0, bk = 0.0;
         for (int k = 0; k < LJ_WAVES_PER_BLOCK; ++k) {
             be += red[k][0];
             bw += red[k][1];
             bc += red[k][2];
+            bk += red[k][3];
         }
-        double* p = a.partials + 4 * blk;
-        p[0] = be;
-        p[1] = bw;
-        p[2] = bc;
+        reinterpret_cast<double4*>(a.partials)[blk] = make_double4(be, bw, bc, bk);
     }
+}
+
+// True once a kernel has raised an error flag on the device (a bad coordinate
+// or an overflowing list row): later force, reduction and integrator kernels
+// of the stream then leave every output as it was.
+__device__ __forceinline__ bool halted(const int32_t* flags) {
+    return flags && (__builtin_nontemporal_load(flags) & LJ_DEV_ERRORS) != 0;
 }
 
 // Fixed-order block sum of partial records [b0, b1): thread t adds records
 // t, t + 1024, ... (four loads in flight per pass), then the waves' sums are
 // added in wave order.  The result is valid in thread 0.
-__device__ double3 span_sum(const double4* __restrict__ p, int64_t b0, int64_t b1) {
-    __shared__ double red[16][3];
+__device__ double4 span_sum(const double4* __restrict__ p, int64_t b0, int64_t b1) {
+    __shared__ double red[16][4];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    double se = 0.0, sw = 0.0, sc = 0.0;
+    double se = 0.0, sw = 0.0, sc = 0.0, sk = 0.0;
     for (int64_t bb = b0 + threadIdx.x; bb < b1; bb += 4 * 1024) {
         double4 v[4];
 #pragma unroll
@@ -87,23 +95,27 @@ __device__ double3 span_sum(const double4* __restrict__ p, int64_t b0, int64_t b
             se += v[u].x;
             sw += v[u].y;
             sc += v[u].z;
+            sk += v[u].w;
         }
     }
     se = wave_sum(se);
     sw = wave_sum(sw);
     sc = wave_sum(sc);
+    sk = wave_sum(sk);
     if (lane == 0) {
         red[wave][0] = se;
         red[wave][1] = sw;
         red[wave][2] = sc;
+        red[wave][3] = sk;
     }
     __syncthreads();
-    double3 t = make_double3(0.0, 0.0, 0.0);
+    double4 t = make_double4(0.0, 0.0, 0.0, 0.0);
     if (threadIdx.x == 0) {
         for (int k = 0; k < 16; ++k) {
             t.x += red[k][0];
             t.y += red[k][1];
             t.z += red[k][2];
+            t.w += red[k][3];
         }
     }
     return t;
@@ -113,7 +125,9 @@ __device__ double3 span_sum(const double4* __restrict__ p, int64_t b0, int64_t b
 // the k-th of split equal contiguous spans of system s's block partials.
 __global__ __launch_bounds__(1024) void k_force_reduce_split(const double4* __restrict__ partials,
                                                              const lj_sys* sys, int split,
+                                                             const int32_t* flags,
                                                              double4* __restrict__ out) {
+    if (halted(flags)) return;
     const int s = blockIdx.x / split, k = blockIdx.x % split;
     const lj_sys& sy = sys[s];
     const int64_t b0 = sy.slice0 / LJ_WAVES_PER_BLOCK;
@@ -121,18 +135,21 @@ __global__ __launch_bounds__(1024) void k_force_reduce_split(const double4* __re
     const int64_t span = (b1 - b0 + split - 1) / split;
     const int64_t lo = b0 + k * span < b1 ? b0 + k * span : b1;
     const int64_t hi = lo + span < b1 ? lo + span : b1;
-    const double3 t = span_sum(partials, lo, hi);
-    if (threadIdx.x == 0) out[blockIdx.x] = make_double4(t.x, t.y, t.z, 0.0);
+    const double4 t = span_sum(partials, lo, hi);
+    if (threadIdx.x == 0) out[blockIdx.x] = t;
 }
 
 // One block per system: the fixed-order sum of its block partials (split = 1)
 // or of its split first-level sums; writes the system's energy, virial and
-// pair count.
+// pair count, and (when `kinetic` is not NULL) the kinetic energy of a
+// kicking force pass.
 __global__ __launch_bounds__(1024) void k_force_reduce(const double4* __restrict__ partials,
                                                        const lj_sys* sys, int split,
                                                        const lj_fconst* fc, double scale,
-                                                       double* energy, double* virial,
-                                                       int64_t* npairs) {
+                                                       const int32_t* flags, double* energy,
+                                                       double* virial, int64_t* npairs,
+                                                       double* kinetic) {
+    if (halted(flags)) return;
     const int s = blockIdx.x;
     const lj_sys& sy = sys[s];
     int64_t b0 = (int64_t)s * split, b1 = b0 + split;
@@ -140,11 +157,12 @@ __global__ __launch_bounds__(1024) void k_force_reduce(const double4* __restrict
         b0 = sy.slice0 / LJ_WAVES_PER_BLOCK;
         b1 = (sy.slice0 + sy.nslices) / LJ_WAVES_PER_BLOCK;
     }
-    const double3 t = span_sum(partials, b0, b1);
+    const double4 t = span_sum(partials, b0, b1);
     if (threadIdx.x == 0) {
         energy[s] = scale * (t.x - t.z * fc[s].vc);
         virial[s] = scale * t.y;
         if (npairs) npairs[s] = (int64_t)(scale * t.z + 0.5);
+        if (kinetic) kinetic[s] = t.w;
     }
 }
 
@@ -157,7 +175,7 @@ __global__ __launch_bounds__(1024) void k_force_reduce(const double4* __restrict
 // list; the thread of a system's k-th row converts its k-th atom.
 template <int LAYOUT>
 __global__ __launch_bounds__(LJ_BLOCK) void k_quantize(const double* __restrict__ pos, int64_t n,
-                                                       const lj_sys* sys,
+                                                       uint32_t qshift, const lj_sys* sys,
                                                        const int32_t* slice_sys, int C,
                                                        const lj_fconst* fc,
                                                        uint4* __restrict__ q32) {
@@ -170,7 +188,8 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_quantize(const double* __restrict_
     const int64_t i = sy.atom0 + t;
     double x, y, z;
     if (LAYOUT == LJ_AOS4) {
-        const double4 q = reinterpret_cast<const double4*>(pos)[i];
+        const double4 q = *reinterpret_cast<const double4*>(
+            reinterpret_cast<const char*>(pos) + (i << qshift));
         x = q.x;
         y = q.y;
         z = q.z;
@@ -185,22 +204,25 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_quantize(const double* __restrict_
 
 // One wavefront per slice; a block's four slices belong to one system
 // (systems own whole 256-row blocks).
-template <int G, bool HALF, int LAYOUT, int PREC, int U>
+template <int G, bool HALF, int LAYOUT, int PREC, int U, bool FS>
 __global__ __launch_bounds__(LJ_BLOCK) void k_force(ForceArgs a) {
+    if (halted(a.halt)) return;
     const int64_t blk = lj_xcd_block(blockIdx.x, gridDim.x);
     const int slice = __builtin_amdgcn_readfirstlane(
         (int)blk * LJ_WAVES_PER_BLOCK + (threadIdx.x >> 6));
     const int sid = __builtin_amdgcn_readfirstlane(a.slice_sys[blk * LJ_WAVES_PER_BLOCK]);
-    double e, w, c;
-    slice_forces<G, HALF, LAYOUT, PREC, U>(a, slice, sid, e, w, c);
-    block_partials(a, blk, e, w, c);
+    double e, w, c, k;
+    slice_forces<G, HALF, LAYOUT, PREC, U, FS>(a, slice, sid, e, w, c, k);
+    block_partials(a, blk, e, w, c, k);
 }
 
 // Half list: the forces from the accumulator, which is cleared for the next
 // evaluation.
 template <int LAYOUT>
 __global__ __launch_bounds__(LJ_BLOCK) void k_acc_out(double* __restrict__ acc, int64_t n16,
-                                                      int64_t n, double* __restrict__ f) {
+                                                      int64_t n, const int32_t* flags,
+                                                      double* __restrict__ f) {
+    if (halted(flags)) return;
     const int64_t i = blockIdx.x * (int64_t)LJ_BLOCK + threadIdx.x;
     if (i >= n) return;
     const double x = acc[i], y = acc[16 * n16 + i], z = acc[32 * n16 + i];
@@ -210,12 +232,12 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_acc_out(double* __restrict__ acc, 
     store_f<LAYOUT>(f, n, i, x, y, z);
 }
 
-template <int G, int U>
+template <int G, int U, bool FS>
 lj_status launch_g(lj_ctx* ctx, const ForceArgs& a, bool half, int layout, int prec,
                    int64_t blocks) {
     dim3 grid((unsigned)blocks), block(LJ_BLOCK);
     hipStream_t s = ctx->stream;
-#define LJ_K(H, L, P) hipLaunchKernelGGL((k_force<G, H, L, P, U>), grid, block, 0, s, a)
+#define LJ_K(H, L, P) hipLaunchKernelGGL((k_force<G, H, L, P, U, FS>), grid, block, 0, s, a)
     if (half) {
         if (layout == LJ_AOS4) {
             if (prec == LJ_FP64) LJ_K(true, LJ_AOS4, LJ_FP64); else LJ_K(true, LJ_AOS4, LJ_MIXED);
@@ -232,6 +254,18 @@ lj_status launch_g(lj_ctx* ctx, const ForceArgs& a, bool half, int layout, int p
 #undef LJ_K
     LJ_HIP(hipGetLastError());
     return LJ_OK;
+}
+
+// Entries in flight per lane (tuning knob: 2, 4 or 8); the force-shifted
+// truncation is built for 4 only (the knob changes speed, never results).
+template <int G>
+lj_status launch_u(lj_ctx* ctx, const ForceArgs& a, bool half, int layout, int prec,
+                   int64_t blocks, bool fs) {
+    if (fs) return launch_g<G, 4, true>(ctx, a, half, layout, prec, blocks);
+    const int u = ctx->tune[LJ_TUNE_FORCE_BATCH];
+    if (u == 2) return launch_g<G, 2, false>(ctx, a, half, layout, prec, blocks);
+    if (u == 8) return launch_g<G, 8, false>(ctx, a, half, layout, prec, blocks);
+    return launch_g<G, 4, false>(ctx, a, half, layout, prec, blocks);
 }
 
 }  // namespace
@@ -256,7 +290,7 @@ int64_t lj_force_partials(const lj_list* l) {
     return lj_force_blocks(l->nslices) + (split > 1 ? (int64_t)l->nsys * split : 0);
 }
 
-lj_fconst lj_make_fconst(double eps, double sigma, double rc, const double box[3]) {
+lj_fconst lj_make_fconst(double eps, double sigma, double rc, const double box[3], int trunc) {
     lj_fconst f = {};
     f.rc2 = rc * rc;
     f.sig2 = sigma * sigma;
@@ -265,11 +299,21 @@ lj_fconst lj_make_fconst(double eps, double sigma, double rc, const double box[3
     f.c48 = 48.0 * eps;
     const double s2 = f.sig2 / f.rc2;
     const double s6 = s2 * s2 * s2;
-    f.vc = 4.0 * eps * s6 * (s6 - 1.0);
+    // V(rc), and Fc = -V'(rc) = 24 eps (sigma/rc)^6 [2 (sigma/rc)^6 - 1] / rc.
+    // Per interacting pair the reduction subtracts vc from the energy: V(rc)
+    // for the simple truncation, V(rc) + rc Fc for the force-shifted one,
+    // whose pair energy V(r) - V(rc) + (r - rc) Fc also adds Fc r (summed in
+    // the kernel).
+    const double v_rc = 4.0 * eps * s6 * (s6 - 1.0);
+    const double f_rc = 24.0 * eps * s6 * (2.0 * s6 - 1.0) / rc;
+    f.fshift = trunc == LJ_TRUNC_FORCE_SHIFT ? 1 : 0;
+    f.fcut = f.fshift ? f_rc : 0.0;
+    f.vc = f.fshift ? v_rc + rc * f_rc : v_rc;
     f.sig2f = (float)f.sig2;
     f.c4f = (float)f.c4;
     f.c24f = (float)f.c24;
     f.c48f = (float)f.c48;
+    f.fcutf = (float)f.fcut;
     // Fixed point for the mixed kernel, and the band around rc^2 in which its
     // r^2 defers to the test on the unquantised positions.  A displacement
     // component from the fixed-point records is off by at most one unit
@@ -294,12 +338,16 @@ lj_fconst lj_make_fconst(double eps, double sigma, double rc, const double box[3
 
 lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int precision,
                            const lj_list* l, const lj_fconst* fc, double* force, double* energy,
-                           double* virial, int64_t* npairs, bool quantized) {
+                           double* virial, int64_t* npairs, const lj_force_opts& o) {
     const int64_t blocks = lj_force_blocks(l->nslices);
-    if (lj_force_partials(l) > ctx->partials_cap)
-        return lj_fail(LJ_E_INVALID, "context partials too small");
+    double* partials = o.partials ? o.partials : ctx->partials;
+    const int64_t cap = o.partials ? o.partials_cap : ctx->partials_cap;
+    if (lj_force_partials(l) > cap) return lj_fail(LJ_E_INVALID, "block partials too small");
     const bool half = l->kind == LJ_LIST_HALF;
     if (half && !l->acc) return lj_fail(LJ_E_INVALID, "half list without its force accumulator");
+    if (half && o.kick != LJ_KICK_NONE)
+        return lj_fail(LJ_E_INVALID, "a kick needs whole rows: full lists only");
+    const int tl = lj_tmpl_layout(layout);
     ForceArgs a;
     a.pos = pos;
     a.force = force;
@@ -312,69 +360,70 @@ lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int preci
     a.row_len = l->row_len;
     a.slice_iters = l->slice_iters;
     a.col = l->col;
-    a.partials = ctx->partials;
+    a.partials = partials;
     a.acc = l->acc;
     a.q32 = l->q32;
     a.n16 = (l->n + 15) / 16;
+    a.halt = &ctx->st->flags;
+    a.qshift = lj_qshift(layout);
+    a.kick = o.kick;
+    a.vel = o.vel;
+    a.hdt = o.hdt;
+    a.write_f = o.write_f ? 1 : 0;
     if (precision != LJ_FP64 && !l->q32)
         return lj_fail(LJ_E_INVALID, "mixed precision without the list's fixed-point buffer");
+    const bool fs = o.trunc == LJ_TRUNC_FORCE_SHIFT;
     lj_status st;
     {
         lj_prof_scope prof(ctx, LJ_PROF_FORCE);
-        if (precision != LJ_FP64 && !quantized) {
+        if (precision != LJ_FP64 && !o.quantized) {
             const dim3 qgrid((unsigned)(l->nslices * (LJ_WAVE / l->lanes) / LJ_BLOCK));
-            if (layout == LJ_AOS4)
+            if (tl == LJ_AOS4)
                 hipLaunchKernelGGL(k_quantize<LJ_AOS4>, qgrid, dim3(LJ_BLOCK), 0, ctx->stream,
-                                   pos, l->n, (const lj_sys*)l->dsys, (const int32_t*)l->slice_sys,
-                                   LJ_WAVE / l->lanes, fc, l->q32);
+                                   pos, l->n, a.qshift, (const lj_sys*)l->dsys,
+                                   (const int32_t*)l->slice_sys, LJ_WAVE / l->lanes, fc, l->q32);
             else
                 hipLaunchKernelGGL(k_quantize<LJ_SOA>, qgrid, dim3(LJ_BLOCK), 0, ctx->stream,
-                                   pos, l->n, (const lj_sys*)l->dsys, (const int32_t*)l->slice_sys,
-                                   LJ_WAVE / l->lanes, fc, l->q32);
+                                   pos, l->n, a.qshift, (const lj_sys*)l->dsys,
+                                   (const int32_t*)l->slice_sys, LJ_WAVE / l->lanes, fc, l->q32);
             LJ_HIP(hipGetLastError());
         }
-        // entries in flight per lane: tuned value
-        const int u = ctx->tune[LJ_TUNE_FORCE_BATCH];
-#define LJ_U(G)                                                                      \
-    (u == 2 ? launch_g<G, 2>(ctx, a, half, layout, precision, blocks)                \
-            : u == 8 ? launch_g<G, 8>(ctx, a, half, layout, precision, blocks)       \
-                     : launch_g<G, 4>(ctx, a, half, layout, precision, blocks))
         switch (l->lanes) {
-            case 1: st = LJ_U(1); break;
-            case 2: st = LJ_U(2); break;
-            case 4: st = LJ_U(4); break;
-            case 8: st = LJ_U(8); break;
-            case 16: st = LJ_U(16); break;
-            case 32: st = LJ_U(32); break;
-            case 64: st = LJ_U(64); break;
+            case 1: st = launch_u<1>(ctx, a, half, tl, precision, blocks, fs); break;
+            case 2: st = launch_u<2>(ctx, a, half, tl, precision, blocks, fs); break;
+            case 4: st = launch_u<4>(ctx, a, half, tl, precision, blocks, fs); break;
+            case 8: st = launch_u<8>(ctx, a, half, tl, precision, blocks, fs); break;
+            case 16: st = launch_u<16>(ctx, a, half, tl, precision, blocks, fs); break;
+            case 32: st = launch_u<32>(ctx, a, half, tl, precision, blocks, fs); break;
+            case 64: st = launch_u<64>(ctx, a, half, tl, precision, blocks, fs); break;
             default: return lj_fail(LJ_E_INVALID, "lanes must be 1, 2, 4, 8, 16, 32 or 64");
         }
-#undef LJ_U
     }
     if (st) return st;
     lj_prof_scope prof(ctx, LJ_PROF_OTHER);
+    const int32_t* flags = &ctx->st->flags;
     if (half) {
         const dim3 grid((unsigned)((l->n + LJ_BLOCK - 1) / LJ_BLOCK)), block(LJ_BLOCK);
-        if (layout == LJ_AOS4)
+        if (tl == LJ_AOS4)
             hipLaunchKernelGGL(k_acc_out<LJ_AOS4>, grid, block, 0, ctx->stream, l->acc, a.n16,
-                               l->n, force);
+                               l->n, flags, force);
         else
             hipLaunchKernelGGL(k_acc_out<LJ_SOA>, grid, block, 0, ctx->stream, l->acc, a.n16,
-                               l->n, force);
+                               l->n, flags, force);
         LJ_HIP(hipGetLastError());
     }
     const int split = lj_force_split(l);
-    const double4* first = reinterpret_cast<const double4*>(ctx->partials);
+    const double4* first = reinterpret_cast<const double4*>(partials);
     if (split > 1) {
-        double4* second = reinterpret_cast<double4*>(ctx->partials) + blocks;
+        double4* second = reinterpret_cast<double4*>(partials) + blocks;
         hipLaunchKernelGGL(k_force_reduce_split, dim3((unsigned)(l->nsys * split)), dim3(1024), 0,
-                           ctx->stream, first, (const lj_sys*)l->dsys, split, second);
+                           ctx->stream, first, (const lj_sys*)l->dsys, split, flags, second);
         LJ_HIP(hipGetLastError());
         first = second;
     }
     hipLaunchKernelGGL(k_force_reduce, dim3((unsigned)l->nsys), dim3(1024), 0, ctx->stream, first,
-                       (const lj_sys*)l->dsys, split, fc, half ? 1.0 : 0.5, energy, virial,
-                       npairs);
+                       (const lj_sys*)l->dsys, split, fc, half ? 1.0 : 0.5, flags, energy, virial,
+                       npairs, o.kick != LJ_KICK_NONE ? o.kinetic : nullptr);
     LJ_HIP(hipGetLastError());
     return LJ_OK;
 }

@@ -25,6 +25,14 @@ struct ForceArgs {
     double* acc;             // half list: spread force accumulator (3 x 16 n16 doubles)
     int64_t n16;
     uint4* q32;              // mixed: fixed-point positions (x, y, z as fractions of the box)
+    const int32_t* halt;     // device status flags: the kernel does nothing once an
+                             // error flag is raised (NULL: never)
+    uint32_t qshift;         // AoS record stride as a shift: 5 (32-byte records) or 6
+                             // (64-byte position-velocity records)
+    int32_t kick;            // LJ_KICK_*
+    double* vel;             // kicked velocities (layout and stride of the positions)
+    double hdt;              // dt / 2
+    int32_t write_f;         // with a kick: also store the forces
 };
 
 __device__ __forceinline__ double r2_rounded(double x, double y, double z) {
@@ -42,6 +50,7 @@ __device__ __forceinline__ void acc_add(double* __restrict__ acc, int64_t n16, i
     unsafeAtomicAdd(acc + 32 * n16 + i, z);
 }
 
+// Forces: 32-byte records (x, y, z, 0) for AoS positions of either stride, or SoA.
 template <int LAYOUT>
 __device__ __forceinline__ void store_f(double* __restrict__ f, int64_t n, int64_t i, double x,
                                         double y, double z) {
@@ -70,13 +79,17 @@ __device__ __forceinline__ double recip(double x) {
     return fma(y, e, y);
 }
 
+// x, y, z of record j: AoS records of 1 << qshift bytes (the position is the
+// first three doubles) addressed with a 32-bit byte offset from a uniform
+// base, or SoA.
 template <int LAYOUT>
-__device__ __forceinline__ void gather_q(const double* __restrict__ pos, int64_t n, int j,
-                                         double& x, double& y, double& z) {
+__device__ __forceinline__ void gather_q(const double* __restrict__ pos, int64_t n,
+                                         uint32_t qshift, int j, double& x, double& y,
+                                         double& z) {
     if (LAYOUT == LJ_AOS4) {
-        // 32-bit byte offset from a uniform base: one dwordx4 + one dwordx2 load
+        // one dwordx4 + one dwordx2 load
         const double4* q = reinterpret_cast<const double4*>(
-            reinterpret_cast<const char*>(pos) + (uint32_t)j * 32u);
+            reinterpret_cast<const char*>(pos) + ((uint32_t)j << qshift));
         x = q->x;
         y = q->y;
         z = q->z;
@@ -88,17 +101,62 @@ __device__ __forceinline__ void gather_q(const double* __restrict__ pos, int64_t
     }
 }
 
+// The kick of one row atom i with its summed force (fx, fy, fz): returns the
+// kinetic energy of the synchronised velocity.  Every product and sum is
+// rounded on its own, as in the integrator's separate kick and drift kernels,
+// so both forms give the same velocities bit for bit.
+template <int LAYOUT>
+__device__ __forceinline__ double kick_row(const ForceArgs& a, int64_t i, double fx, double fy,
+                                           double fz) {
+#pragma clang fp contract(off)
+    double vx, vy, vz, vw = 0.0;
+    double4* rec = nullptr;
+    if (LAYOUT == LJ_AOS4) {
+        rec = reinterpret_cast<double4*>(reinterpret_cast<char*>(a.vel) + (i << a.qshift));
+        const double4 v = *rec;
+        vx = v.x;
+        vy = v.y;
+        vz = v.z;
+        vw = v.w;
+    } else {
+        vx = a.vel[i];
+        vy = a.vel[a.n + i];
+        vz = a.vel[2 * a.n + i];
+    }
+    const double h = a.hdt;
+    vx = vx + h * fx;
+    vy = vy + h * fy;
+    vz = vz + h * fz;
+    const double ke = 0.5 * ((vx * vx + vy * vy) + vz * vz);
+    if (a.kick == LJ_KICK_LEAP) {
+        vx = vx + h * fx;
+        vy = vy + h * fy;
+        vz = vz + h * fz;
+    }
+    if (LAYOUT == LJ_AOS4) {
+        *rec = make_double4(vx, vy, vz, vw);
+    } else {
+        a.vel[i] = vx;
+        a.vel[a.n + i] = vy;
+        a.vel[2 * a.n + i] = vz;
+    }
+    return ke;
+}
+
 // Loads are issued U entries at a time, and the indices of the next U
 // entries are requested before the current ones are computed, so each
 // wavefront keeps up to 3U gathers and U index loads in flight (the
 // load/compute overlap that software pipelining gives a CPU core).
 // The forces of one slice of system sid, computed by the calling wavefront
 // (C = 64 / G rows, G lanes per row); returns the lane's shares of the
-// energy 4 eps (A - B), the virial 24 eps (2A - B) and the pair count, for the
-// caller to sum in a fixed order.
-template <int G, bool HALF, int LAYOUT, int PREC, int U>
+// energy, the virial, the pair count and (with a kick) the kinetic energy,
+// for the caller to sum in a fixed order.  FS: the force-shifted truncation
+// (Sec. III.A), in which each interacting pair's force loses Fc = -V'(rc)
+// along the pair and its energy gains (r - rc) Fc, so that both vanish at rc.
+template <int G, bool HALF, int LAYOUT, int PREC, int U, bool FS>
 __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int sid,
-                                             double& e_out, double& w_out, double& c_out) {
+                                             double& e_out, double& w_out, double& c_out,
+                                             double& k_out) {
     constexpr int C = LJ_WAVE / G;
     const int lane = threadIdx.x & (LJ_WAVE - 1);
     const lj_sys& sy = a.sys[sid];
@@ -113,12 +171,12 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
     const double ibx = sy.inv_box[0], iby = sy.inv_box[1], ibz = sy.inv_box[2];
     const double rc2 = fc.rc2;
     double qx, qy, qz;
-    gather_q<LAYOUT>(a.pos, a.n, i, qx, qy, qz);
+    gather_q<LAYOUT>(a.pos, a.n, a.qshift, i, qx, qy, qz);
 
     const char* colbase = reinterpret_cast<const char*>(
         a.col + sy.col0 + (int64_t)(slice - sy.slice0) * (sy.cap / G) * LJ_WAVE);
     const uint32_t lane_off = (uint32_t)lane * 4u;
-    double fx = 0.0, fy = 0.0, fz = 0.0, sA = 0.0, sB = 0.0;
+    double fx = 0.0, fy = 0.0, fz = 0.0, sA = 0.0, sB = 0.0, sR = 0.0;
     int cnt = 0;
 
     // slot of step `it`, clamped into the slice so that every index load is
@@ -135,6 +193,8 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
     // the force constants as values, read once
     const double sig2 = fc.sig2, c24 = fc.c24, c48 = fc.c48;
     const float sig2f = fc.sig2f, c24f = fc.c24f, c48f = fc.c48f;
+    const double fcut = fc.fcut;
+    const float fcutf = fc.fcutf;
     const double qs0 = fc.qs[0], qs1 = fc.qs[1], qs2 = fc.qs[2];
     const double rc2lo = fc.rc2lo, rc2hi = fc.rc2hi;
     // mixed: the row atom's fixed-point record; whether the lane met an entry
@@ -142,19 +202,31 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
     uint4 qi4 = make_uint4(0u, 0u, 0u, 0u);
     if constexpr (PREC != LJ_FP64) qi4 = a.q32[i];
     bool had_amb = false;
-    // pair terms of an interacting entry from its r^2 (mixed: FP32 terms)
-    auto pair_terms = [&](double r2, bool m, double& fs, double& sr6d) {
+    // pair terms of an interacting entry from its r^2 (mixed: FP32 terms);
+    // rr: the pair's distance r for the force-shifted energy (0 if masked)
+    auto pair_terms = [&](double r2, bool m, double& fs, double& sr6d, double& rr) {
         if constexpr (PREC == LJ_FP64) {
             const double ir2 = m ? recip(r2) : 0.0;
             const double sr2 = sig2 * ir2;
             const double sr6 = sr2 * sr2 * sr2;
             fs = ir2 * (sr6 * fma(c48, sr6, -c24));
             sr6d = sr6;
+            if constexpr (FS) {
+                const double rd = m ? __builtin_sqrt(r2) : 0.0;
+                fs = fma(-fcut * rd, ir2, fs);     // fs - Fc / r
+                rr = rd;
+            }
         } else {
             const float ir2 = m ? __builtin_amdgcn_rcpf((float)r2) : 0.0f;
             const float sr2 = sig2f * ir2;
             const float sr6 = sr2 * sr2 * sr2;
-            fs = (double)(ir2 * (sr6 * fmaf(c48f, sr6, -c24f)));
+            float fsf = ir2 * (sr6 * fmaf(c48f, sr6, -c24f));
+            if constexpr (FS) {
+                const float rf = m ? __builtin_sqrtf((float)r2) : 0.0f;
+                fsf = fmaf(-fcutf * rf, ir2, fsf);
+                rr = (double)rf;
+            }
+            fs = (double)fsf;
             sr6d = (double)sr6;
         }
     };
@@ -170,7 +242,8 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
         uint4 qv[U];
         if constexpr (PREC == LJ_FP64) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) gather_q<LAYOUT>(a.pos, a.n, jn[u], px[u], py[u], pz[u]);
+            for (int u = 0; u < U; ++u)
+                gather_q<LAYOUT>(a.pos, a.n, a.qshift, jn[u], px[u], py[u], pz[u]);
         } else {
 #pragma unroll
             for (int u = 0; u < U; ++u) qv[u] = a.q32[jn[u]];
@@ -185,7 +258,7 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const bool valid = (it0 + u < iters) && ((it0 + u) * G < lim);
-            double tx, ty, tz, fs, sr6d;
+            double tx, ty, tz, fs, sr6d, rr = 0.0;
             bool m;
             if constexpr (PREC == LJ_FP64) {
                 tx = px[u] - qx;
@@ -196,17 +269,19 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
                 tz = fma(-rint(tz * ibz), bz, tz);
                 const double r2 = r2_rounded(tx, ty, tz);
                 m = valid && (r2 < rc2);
-                pair_terms(r2, m, fs, sr6d);
+                pair_terms(r2, m, fs, sr6d, rr);
             } else {
                 fixed_disp(qv[u], tx, ty, tz);
                 const double r2 = r2_rounded(tx, ty, tz);
                 m = valid && (r2 < rc2lo);
                 had_amb = had_amb || (valid && !(r2 < rc2lo) && (r2 < rc2hi));
-                pair_terms(r2, m, fs, sr6d);
+                pair_terms(r2, m, fs, sr6d, rr);
             }
             // energy and virial from two sums: sum (sigma/r)^12 and sum (sigma/r)^6
+            // (and sum r for the force-shifted truncation)
             sA = fma(sr6d, sr6d, sA);
             sB += sr6d;
+            if constexpr (FS) sR += rr;
             cnt += m ? 1 : 0;
             fx = fma(-fs, tx, fx);
             fy = fma(-fs, ty, fy);
@@ -225,7 +300,7 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
                 const double r2 = r2_rounded(tx, ty, tz);
                 if (r2 < rc2lo || !(r2 < rc2hi)) continue;
                 double ex, ey, ez;
-                gather_q<LAYOUT>(a.pos, a.n, j, ex, ey, ez);
+                gather_q<LAYOUT>(a.pos, a.n, a.qshift, j, ex, ey, ez);
                 ex = ex - qx;
                 ey = ey - qy;
                 ez = ez - qz;
@@ -233,10 +308,11 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
                 ey = fma(-rint(ey * iby), by, ey);
                 ez = fma(-rint(ez * ibz), bz, ez);
                 if (!(r2_rounded(ex, ey, ez) < rc2)) continue;
-                double fs, sr6d;
-                pair_terms(r2, true, fs, sr6d);
+                double fs, sr6d, rr = 0.0;
+                pair_terms(r2, true, fs, sr6d, rr);
                 sA = fma(sr6d, sr6d, sA);
                 sB += sr6d;
+                if constexpr (FS) sR += rr;
                 cnt += 1;
                 fx = fma(-fs, tx, fx);
                 fy = fma(-fs, ty, fy);
@@ -252,16 +328,26 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
         fy += __shfl_xor(fy, d, LJ_WAVE);
         fz += __shfl_xor(fz, d, LJ_WAVE);
     }
+    double ke = 0.0;
     if (g == 0 && row_ok) {
-        if (HALF)
+        if (HALF) {
             acc_add(a.acc, a.n16, i, fx, fy, fz);
-        else
+        } else if (a.kick == LJ_KICK_NONE) {
             store_f<LAYOUT>(a.force, a.n, i, fx, fy, fz);
+        } else {
+            ke = kick_row<LAYOUT>(a, i, fx, fy, fz);
+            if (a.write_f) store_f<LAYOUT>(a.force, a.n, i, fx, fy, fz);
+        }
     }
-    // per lane: 4 eps (A - B) and 24 eps (2A - B)
+    // per lane: 4 eps (A - B) [+ Fc sum r] and 24 eps (2A - B) [- Fc sum r]
     e_out = fc.c4 * (sA - sB);
     w_out = fc.c24 * (2.0 * sA - sB);
+    if constexpr (FS) {
+        e_out = fma(fcut, sR, e_out);
+        w_out = fma(-fcut, sR, w_out);
+    }
     c_out = (double)cnt;
+    k_out = ke;
 }
 
 }  // namespace ljf

@@ -69,8 +69,12 @@ struct lj_sys {
 
 // Force constants of one system.
 struct lj_fconst {
-    double rc2, sig2, c4, c24, c48, vc;   // rc^2, sigma^2, 4 eps, 24 eps, 48 eps, V(rc)
-    float sig2f, c4f, c24f, c48f;
+    double rc2, sig2, c4, c24, c48;       // rc^2, sigma^2, 4 eps, 24 eps, 48 eps
+    double vc;                            // energy subtracted per interacting pair: V(rc),
+                                          // or V(rc) + rc Fc when force-shifted
+    double fcut;                          // force-shifted: Fc = -V'(rc); else 0
+    int32_t fshift, pad0;                 // 1: force-shifted truncation
+    float sig2f, c4f, c24f, c48f, fcutf;
     // Mixed precision: positions as 32-bit fixed point, x = u * L / 2^32
     double qinv[3];        // 2^32 / L per dimension (quantisation)
     double qs[3];          // L / 2^32 per dimension: one fixed-point unit (exact)
@@ -88,6 +92,11 @@ struct lj_dev_status {
 };
 #define LJ_DEV_BAD_POSITION 1
 #define LJ_DEV_ROW_OVERFLOW 2
+#define LJ_DEV_STALE 4          // an integrator step found an atom moved more than skin/2
+                                // since the list was built (fixed rebuild cadence)
+#define LJ_DEV_RESTORED 8       // an integrator run stopped and restored its last good step
+// errors after which force and integrator kernels leave their outputs as they were
+#define LJ_DEV_ERRORS (LJ_DEV_BAD_POSITION | LJ_DEV_ROW_OVERFLOW)
 
 // Row statistics of one system of a list, written by its latest build.
 struct lj_list_stats {
@@ -144,6 +153,7 @@ struct lj_cells {
 
 struct lj_list {
     int device;                    // device of the context that built it
+    hipStream_t stream;            // stream of its latest build or update
     int nsys;
     int64_t n;
     int kind;
@@ -178,14 +188,25 @@ lj_status lj_hip_fail(hipError_t e, const char* what);
         if (e_ != hipSuccess) return lj_hip_fail(e_, #call);    \
     } while (0)
 
+// ------------------------------------------------------ position layouts
+// Kernels are built for two forms: AoS records whose first three doubles are
+// (x, y, z) -- LJ_AOS4 (32-byte records) and LJ_AOS8 (64-byte records whose
+// second half the caller uses, e.g. for velocities) -- and LJ_SOA.  The AoS
+// record stride is passed as a shift.
+inline int lj_tmpl_layout(int layout) { return layout == LJ_SOA ? LJ_SOA : LJ_AOS4; }
+inline uint32_t lj_qshift(int layout) { return layout == LJ_AOS8 ? 6u : 5u; }
+
 // -------------------------------------------------------------- launchers
-// cells (lj_cells.hip)
-lj_status lj_launch_cells(lj_ctx* ctx, const double* pos, int layout, lj_cells* c);
+// cells (lj_cells.hip).  gate: device word; when not NULL the kernels do
+// nothing unless it is non-zero (a rebuild decided on the device).
+lj_status lj_launch_cells(lj_ctx* ctx, const double* pos, int layout, lj_cells* c,
+                          const int32_t* gate = nullptr);
 int64_t lj_scan_workspace(int64_t m);
 // neighbor list (lj_neigh.hip): rebuild every system of l from cells c; the
 // per-system statistics (longest row, entries) follow at once with `stats`,
 // else when they are next asked for (lj_launch_list_stats)
-lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l, bool stats);
+lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l, bool stats,
+                              const int32_t* gate = nullptr);
 lj_status lj_launch_list_stats(hipStream_t s, lj_list* l);
 // lanes per row the list build of a new list uses (tuning knob, <= lanes)
 int lj_build_lanes(const lj_ctx* ctx, int lanes);
@@ -196,12 +217,37 @@ int64_t lj_force_blocks(int64_t nslices);
 // (double4) the context must hold for list l.
 int lj_force_split(const lj_list* l);
 int64_t lj_force_partials(const lj_list* l);
+// Momentum update folded into the force pass (the impulse form of Alg. 1),
+// full lists only: once a row's force F is summed, its atom's velocity is
+// kicked in place.
+//   LJ_KICK_SYNC : v += F dt/2 (the kick that ends a velocity-Verlet step)
+//   LJ_KICK_LEAP : v += F dt/2 twice, each rounded as a separate kick: the
+//                  kick that ends this step and the one that opens the next
+//                  (the next drift then only moves the atoms)
+// Either way the kinetic energy of the synchronised velocity (after the
+// first kick) joins the block partials.
+#define LJ_KICK_NONE 0
+#define LJ_KICK_SYNC 1
+#define LJ_KICK_LEAP 2
+
 // LJ_MIXED needs the list's fixed-point position buffer (lj_list_ensure_q32,
-// called before any launch that a graph may capture); `quantized`: the buffer
-// already holds pos in fixed point (written by the integrator's drift).
+// called before any launch that a graph may capture).
+struct lj_force_opts {
+    bool quantized = false;       // mixed: the list's fixed-point buffer already holds pos
+                                  // (written by the integrator's drift)
+    double* partials = nullptr;   // block partials (double4 records); NULL: the context's
+    int64_t partials_cap = 0;     // their capacity in records
+    int trunc = LJ_TRUNC_SHIFT;   // must match the constants in fc
+    int kick = 0;                 // LJ_KICK_* (lj_force_loop.h), full lists only
+    double* vel = nullptr;        // kicked velocities, layout of the positions
+    double hdt = 0.0;             // dt / 2
+    bool write_f = true;          // with a kick: also store the forces
+    double* kinetic = nullptr;    // with a kick: per-system kinetic energy
+};
 lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int precision,
                            const lj_list* l, const lj_fconst* fc, double* force, double* energy,
-                           double* virial, int64_t* npairs, bool quantized = false);
+                           double* virial, int64_t* npairs,
+                           const lj_force_opts& o = lj_force_opts());
 // host and device: one coordinate in the mixed kernel's fixed point,
 // rint(x 2^32 / L) mod 2^32
 __host__ __device__ __forceinline__ uint32_t lj_fix32(double x, double inv_unit) {
@@ -210,20 +256,22 @@ __host__ __device__ __forceinline__ uint32_t lj_fix32(double x, double inv_unit)
 lj_status lj_list_ensure_q32(lj_list* l);
 // integrator (lj_nve.hip)
 lj_status lj_nve_make(lj_ctx* ctx, double* pos, double* vel, double* force, int32_t layout,
-                      const lj_fconst* hfc, int32_t precision, lj_list* list, double dt,
-                      int32_t rebuild_every, double* log, int64_t log_rows, lj_nve** out);
+                      const lj_fconst* hfc, int32_t precision, int32_t trunc, lj_list* list,
+                      double dt, int32_t rebuild_every, double* log, int64_t log_rows,
+                      lj_nve** out);
 lj_status lj_nve_start(lj_nve* s);
 lj_status lj_nve_advance(lj_nve* s, int32_t nsteps, int32_t use_graph);
 void lj_nve_release(lj_nve* s);
-int64_t lj_nve_step_count(const lj_nve* s);
+// steps completed since lj_nve_start, read from the device (synchronous)
+lj_status lj_nve_device_steps(lj_nve* s, int64_t* steps);
 lj_status lj_list_ensure_cells(lj_ctx* ctx, lj_list* l);
 // exclusive scan of m int32 values into out[0..m] (out[m] = total); with
 // clear_in the input is zeroed as it is read
 lj_status lj_launch_scan(hipStream_t s, int32_t* in, int32_t* out, int64_t m, int32_t* work,
-                         bool clear_in);
+                         bool clear_in, const int32_t* gate = nullptr);
 lj_status lj_launch_zero(hipStream_t s, void* p, int64_t bytes);
 // host: force constants of one system with box lengths box[3]
-lj_fconst lj_make_fconst(double eps, double sigma, double rc, const double box[3]);
+lj_fconst lj_make_fconst(double eps, double sigma, double rc, const double box[3], int trunc);
 
 // ------------------------------------------------------- device helpers
 // Logical block index that gives each XCD a contiguous range of blocks

@@ -55,7 +55,12 @@ struct NeighArgs {
                            // candidates tested, unused
     int32_t* col;
     lj_dev_status* st;     // a row that overflows its capacity raises a flag here
+    const int32_t* gate;   // when not NULL, build only if *gate != 0 (decided on the device)
 };
+
+__device__ __forceinline__ bool gated_off(const int32_t* gate) {
+    return gate && __builtin_nontemporal_load(gate) == 0;
+}
 
 __device__ __forceinline__ double r2_rounded(double x, double y, double z) {
 #pragma clang fp contract(off)
@@ -247,6 +252,7 @@ __device__ __forceinline__ double group_bcast(double v) {
 
 template <int G, int GB, bool HALF, bool ANYFULL>
 __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
+    if (gated_off(a.gate)) return;
     constexpr int CB = LJ_WAVE / GB;   // rows per wavefront in the build
     constexpr int C = LJ_WAVE / G;     // rows per slice of the layout
     constexpr int SL = C * GB;         // lanes of the wavefront that hold one slice
@@ -488,6 +494,7 @@ __device__ __forceinline__ double dword_pair(unsigned int lo, unsigned int hi) {
 // spills to scratch, which costs more than the eighth wavefront gains.
 template <int G, bool HALF, bool ANYFULL>
 __global__ __launch_bounds__(LJ_BLOCK, 7) void k_neigh_rows(NeighArgs a) {
+    if (gated_off(a.gate)) return;
     constexpr int C = LJ_WAVE / G;          // rows per slice of the layout
     constexpr int RW = C > 8 ? C : 8;       // rows per wavefront: whole slices
     __shared__ RowTable tables[LJ_WAVES_PER_BLOCK];
@@ -946,8 +953,10 @@ int lj_build_lanes(const lj_ctx* ctx, int lanes) {
     return gb > lanes ? lanes : gb;
 }
 
-lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l, bool stats) {
+lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l, bool stats,
+                              const int32_t* gate) {
     NeighArgs a;
+    a.gate = gate;
     a.nslices = l->nslices;
     a.sys = l->dsys;
     a.slice_sys = l->slice_sys;

@@ -27,7 +27,9 @@ STATUS_NAMES = {0: "LJ_OK", -1: "LJ_E_INVALID", -2: "LJ_E_BOX", -3: "LJ_E_POSITI
                 -8: "LJ_E_NODEVICE"}
 LJ_LIST_HALF, LJ_LIST_FULL = 0, 1
 LJ_FP64, LJ_MIXED = 0, 1
-LJ_AOS4, LJ_SOA = 0, 1
+LJ_AOS4, LJ_SOA, LJ_AOS8 = 0, 1, 2
+LJ_TRUNC_SHIFT, LJ_TRUNC_FORCE_SHIFT = 0, 1
+LOG_COLS = 6   # integrator log: PE, KE, W, max displacement, pairs, rebuilt
 
 # every entry point declared in include/lj.h
 EXPORTS = ["lj_create", "lj_destroy", "lj_set_stream", "lj_sync", "lj_build_cells",
@@ -37,7 +39,7 @@ EXPORTS = ["lj_create", "lj_destroy", "lj_set_stream", "lj_sync", "lj_build_cell
            "lj_nve_steps", "lj_nve_free", "lj_build_neighbors_batch", "lj_forces_batch",
            "lj_list_sys_info", "lj_nve_create_batch",
            "lj_profile_begin", "lj_profile_end", "lj_tune_set", "lj_tune_get", "lj_last_error"]
-LJ_TUNE_BUILD_LANES, LJ_TUNE_FORCE_BATCH, LJ_TUNE_CELL_DIV, LJ_TUNE_N = 0, 1, 2, 3
+LJ_TUNE_BUILD_LANES, LJ_TUNE_FORCE_BATCH, LJ_TUNE_CELL_DIV, LJ_TUNE_KICK, LJ_TUNE_N = 0, 1, 2, 3, 4
 LJ_PROF_CELLS, LJ_PROF_NEIGH, LJ_PROF_FORCE, LJ_PROF_OTHER, LJ_PROF_INTEGRATE = 0, 1, 2, 3, 4
 LJ_PROF_N = 5
 PROF_PHASES = ("cells", "neigh", "force", "other", "integrate")
@@ -98,13 +100,14 @@ def load(path: str = LIB_PATH):
         "lj_list_pairs": ([_VP, _VP, i64, _VP, ctypes.POINTER(i64)]),
         "lj_list_free": ([_VP]),
         "lj_list_device_view": ([_VP, ctypes.POINTER(ListView)]),
-        "lj_forces": ([_VP, _VP, i64, i32, _D3, dbl, dbl, dbl, _VP, i32, _VP, _VP, _VP, _VP]),
-        "lj_nve_create": ([_VP, _VP, _VP, _VP, i64, i32, _D3, dbl, dbl, dbl, i32, _VP, dbl, i32,
-                           _VP, i64, PP]),
-        "lj_nve_create_batch": ([_VP, _VP, _VP, _VP, i32, _VP, _VP, _VP, i32, _VP, dbl, i32,
-                                 _VP, i64, PP]),
+        "lj_forces": ([_VP, _VP, i64, i32, _D3, dbl, dbl, dbl, _VP, i32, i32, _VP, _VP, _VP,
+                       _VP]),
+        "lj_nve_create": ([_VP, _VP, _VP, _VP, i64, i32, _D3, dbl, dbl, dbl, i32, i32, _VP, dbl,
+                           i32, _VP, i64, PP]),
+        "lj_nve_create_batch": ([_VP, _VP, _VP, _VP, i32, _VP, _VP, _VP, i32, i32, _VP, dbl,
+                                 i32, _VP, i64, PP]),
         "lj_build_neighbors_batch": ([_VP, _VP, i32, i32, _VP, _VP, _VP, dbl, i32, i32, PP]),
-        "lj_forces_batch": ([_VP, _VP, i32, _VP, _VP, _VP, _VP, i32, _VP, _VP, _VP, _VP]),
+        "lj_forces_batch": ([_VP, _VP, i32, _VP, _VP, _VP, _VP, i32, i32, _VP, _VP, _VP, _VP]),
         "lj_list_sys_info": ([_VP, i32, ctypes.POINTER(i64), ctypes.POINTER(i32),
                               ctypes.POINTER(i64), ctypes.POINTER(i32)]),
         "lj_nve_init": ([_VP]),
@@ -144,15 +147,26 @@ def _ptr(t) -> int:
 
 
 def _pos_layout(pos) -> Tuple[int, int]:
-    """(n, layout) from a tensor's shape: (n, 4) -> AOS4, (3, n) -> SOA."""
+    """(n, layout) from a tensor's shape: (n, 4) -> AOS4, (n, 8) -> AOS8
+    (position and velocity records), (3, n) -> SOA."""
     import torch
     if pos.dtype != torch.float64:
         raise TypeError("positions must be float64")
     if pos.dim() == 2 and pos.shape[1] == 4:
         return int(pos.shape[0]), LJ_AOS4
+    if pos.dim() == 2 and pos.shape[1] == 8:
+        return int(pos.shape[0]), LJ_AOS8
     if pos.dim() == 2 and pos.shape[0] == 3:
         return int(pos.shape[1]), LJ_SOA
-    raise ValueError("positions must be (n, 4) [AOS4] or (3, n) [SOA]")
+    raise ValueError("positions must be (n, 4) [AOS4], (n, 8) [AOS8] or (3, n) [SOA]")
+
+
+def _force_like(pos, layout):
+    """A force array for positions in `layout` (AOS8 positions give AOS4 forces)."""
+    import torch
+    if layout == LJ_AOS8:
+        return torch.empty((pos.shape[0], 4), dtype=pos.dtype, device=pos.device)
+    return torch.empty_like(pos)
 
 
 class Context:
@@ -310,21 +324,22 @@ def lj_update_neighbors(ctx: Context, pos, box, nlist: NeighborList) -> Neighbor
 
 
 def lj_forces(ctx: Context, pos, box, eps: float, sigma: float, rc: float,
-              nlist: NeighborList, precision: int = LJ_FP64, force=None, out=None):
+              nlist: NeighborList, precision: int = LJ_FP64, force=None, out=None,
+              trunc: int = LJ_TRUNC_SHIFT):
     """Launch the force kernel (asynchronous).  force: tensor shaped like pos
-    (allocated if None); out: float64 device tensor of 2 receiving energy and
-    virial (allocated if None).  Returns (force, energy, virial, npairs) as
-    device tensors."""
+    ((n, 4) for AOS8 positions; allocated if None); out: float64 device tensor
+    of 2 receiving energy and virial (allocated if None).  Returns (force,
+    energy, virial, npairs) as device tensors."""
     import torch
     n, layout = _pos_layout(pos)
     if force is None:
-        force = torch.empty_like(pos)
+        force = _force_like(pos, layout)
     if out is None:
         out = torch.empty(2, dtype=torch.float64, device=pos.device)
     cnt = torch.empty(1, dtype=torch.int64, device=pos.device)
     _check(load().lj_forces(ctx.h, _ptr(pos), n, layout, _box(box), float(eps), float(sigma),
-                            float(rc), nlist.h, int(precision), _ptr(force), _ptr(out),
-                            out.data_ptr() + 8, _ptr(cnt)), "lj_forces")
+                            float(rc), nlist.h, int(precision), int(trunc), _ptr(force),
+                            _ptr(out), out.data_ptr() + 8, _ptr(cnt)), "lj_forces")
     return force, out[0:1], out[1:2], cnt
 
 
@@ -354,56 +369,67 @@ def lj_build_neighbors_batch(ctx: Context, pos, n, box, rc, skin: float,
 
 
 def lj_forces_batch(ctx: Context, pos, nlist: NeighborList, eps, sigma, rc,
-                    precision: int = LJ_FP64, force=None):
+                    precision: int = LJ_FP64, force=None, trunc: int = LJ_TRUNC_SHIFT):
     """(force, energy[nsys], virial[nsys], npairs[nsys]) as device tensors."""
     import torch
     _, layout = _pos_layout(pos)
     eps, sigma, rc = _harr(eps, np.float64), _harr(sigma, np.float64), _harr(rc, np.float64)
     ns = int(eps.size)
     if force is None:
-        force = torch.empty_like(pos)
+        force = _force_like(pos, layout)
     e = torch.empty(ns, dtype=torch.float64, device=pos.device)
     w = torch.empty(ns, dtype=torch.float64, device=pos.device)
     c = torch.empty(ns, dtype=torch.int64, device=pos.device)
     _check(load().lj_forces_batch(ctx.h, _ptr(pos), layout, nlist.h, eps.ctypes.data,
-                                  sigma.ctypes.data, rc.ctypes.data, int(precision), _ptr(force),
-                                  _ptr(e), _ptr(w), _ptr(c)), "lj_forces_batch")
+                                  sigma.ctypes.data, rc.ctypes.data, int(precision), int(trunc),
+                                  _ptr(force), _ptr(e), _ptr(w), _ptr(c)), "lj_forces_batch")
     return force, e, w, c
 
 
 class NVE:
     """Velocity-Verlet integrator bound to device arrays pos, vel, force (same
-    layout) and a device log of log_rows x 5 doubles (lj_nve_create)."""
+    layout; with (n, 8) AOS8 position-velocity records vel is ignored: the
+    velocities are the second half of each record, and force is (n, 4)) and a
+    device log of log_rows x 6 doubles (lj_nve_create).  rebuild_every = 0
+    rebuilds the list when an atom has moved more than skin/2."""
 
     def __init__(self, ctx: Context, pos, vel, force, box, eps, sigma, rc,
                  nlist: NeighborList, dt: float, rebuild_every: int = 10,
-                 precision: int = LJ_FP64, log_rows: int = 0, batch: bool = False):
-        """Single system: box (3,), scalar eps, sigma, rc; log (log_rows, 5).
-        batch=True: per-system arrays eps, sigma, rc; log (log_rows, nsys, 5)."""
+                 precision: int = LJ_FP64, log_rows: int = 0, batch: bool = False,
+                 trunc: int = LJ_TRUNC_SHIFT):
+        """Single system: box (3,), scalar eps, sigma, rc; log (log_rows, 6).
+        batch=True: per-system arrays eps, sigma, rc; log (log_rows, nsys, 6)."""
         import torch
         n, layout = _pos_layout(pos)
-        for t in (vel, force):
-            if t.shape != pos.shape or t.dtype != pos.dtype:
-                raise ValueError("vel and force must match pos in shape and dtype")
+        if layout == LJ_AOS8:
+            if force.shape != (n, 4) or force.dtype != pos.dtype:
+                raise ValueError("AOS8 records need an (n, 4) float64 force array")
+            vel_ptr = pos.data_ptr() + 32
+        else:
+            for t in (vel, force):
+                if t.shape != pos.shape or t.dtype != pos.dtype:
+                    raise ValueError("vel and force must match pos in shape and dtype")
+            vel_ptr = _ptr(vel)
         self.ctx, self.pos, self.vel, self.force, self.nlist = ctx, pos, vel, force, nlist
         h = _VP()
         if batch:
             eps, sigma, rc = _harr(eps, np.float64), _harr(sigma, np.float64), _harr(rc, np.float64)
             ns = int(eps.size)
-            self.log = torch.zeros((max(log_rows, 1), ns, 5), dtype=torch.float64,
+            self.log = torch.zeros((max(log_rows, 1), ns, LOG_COLS), dtype=torch.float64,
                                    device=pos.device)
-            _check(load().lj_nve_create_batch(ctx.h, _ptr(pos), _ptr(vel), _ptr(force), layout,
+            _check(load().lj_nve_create_batch(ctx.h, _ptr(pos), vel_ptr, _ptr(force), layout,
                                               eps.ctypes.data, sigma.ctypes.data, rc.ctypes.data,
-                                              int(precision), nlist.h, float(dt),
+                                              int(precision), int(trunc), nlist.h, float(dt),
                                               int(rebuild_every), _ptr(self.log), int(log_rows),
                                               ctypes.byref(h)), "lj_nve_create_batch")
         else:
-            self.log = torch.zeros((max(log_rows, 1), 5), dtype=torch.float64, device=pos.device)
-            _check(load().lj_nve_create(ctx.h, _ptr(pos), _ptr(vel), _ptr(force), n, layout,
+            self.log = torch.zeros((max(log_rows, 1), LOG_COLS), dtype=torch.float64,
+                                   device=pos.device)
+            _check(load().lj_nve_create(ctx.h, _ptr(pos), vel_ptr, _ptr(force), n, layout,
                                         _box(box), float(eps), float(sigma), float(rc),
-                                        int(precision), nlist.h, float(dt), int(rebuild_every),
-                                        _ptr(self.log), int(log_rows), ctypes.byref(h)),
-                   "lj_nve_create")
+                                        int(precision), int(trunc), nlist.h, float(dt),
+                                        int(rebuild_every), _ptr(self.log), int(log_rows),
+                                        ctypes.byref(h)), "lj_nve_create")
         self.h = h
 
     def init(self):

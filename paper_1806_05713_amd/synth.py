@@ -150,7 +150,7 @@ def vacancy_system(N: int, rho: float, delta: float, rng: np.random.Generator,
 # ---------------------------------------------------------------------------
 
 SEEDS = {"lj4k": 1806, "lj131k": 5713, "lj4m": 2018, "lj500k": 4096, "batch512": 512,
-         "perm": 77}
+         "perm": 77, "lj4m_jit": 2019}
 
 
 def lj4k() -> System:
@@ -166,6 +166,13 @@ def lj131k() -> System:
 def lj4m() -> System:
     """4,000,000 atoms (100^3 FCC cells), rho = 0.85, Maxwell T = 1.0, rc = 2.5, skin 0.3."""
     return fcc_system(100, 0.85, 0.0, SEEDS["lj4m"], 2.5, 0.3, T=1.0, name="lj4m")
+
+
+def lj4m_jittered() -> System:
+    """The 4M-atom fluid's geometry (100^3 FCC cells, rho = 0.85, rc = 2.5,
+    skin 0.3) with every coordinate jittered by U(-0.1, 0.1): forces of the
+    size of a fluid's instead of a perfect lattice's roundoff (parity checks)."""
+    return fcc_system(100, 0.85, 0.1, SEEDS["lj4m_jit"], 2.5, 0.3, name="lj4m-jit")
 
 
 def lj500k() -> System:

@@ -39,7 +39,7 @@ def test_argument_errors_without_device():
     box = (ctypes.c_double * 3)(10.0, 10.0, 10.0)
     assert L.lj_build_neighbors(None, None, 10, 0, box, 3.0, 0.3, 0, 0, None,
                                 ctypes.byref(out)) == lj.LJ_E_INVALID
-    assert L.lj_forces(None, None, 10, 0, box, 1.0, 1.0, 3.0, None, 0, None, None, None,
+    assert L.lj_forces(None, None, 10, 0, box, 1.0, 1.0, 3.0, None, 0, 0, None, None, None,
                        None) == lj.LJ_E_INVALID
     assert L.lj_list_info(None, None) == lj.LJ_E_INVALID
     assert L.lj_cells_info(None, None, None) == lj.LJ_E_INVALID

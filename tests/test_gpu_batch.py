@@ -84,7 +84,7 @@ def test_batch_pairs_and_forces(lj, ctx, oracle, kind, layout, build_lanes):
             mine = mine[mine[:, 0] < mine[:, 1]]
         assert np.array_equal(canon(mine), ref), f"system {s}"
         Fr, Er, Wr, nr = oracle.forces(sy.pos, sy.box, 1.0, 1.0, sy.rc, rp, col)
-        scale = max(np.abs(Fr).max(), 24.0)
+        scale = np.abs(Fr).max()
         assert np.abs(f[off[s]:off[s + 1]] - Fr).max() <= 1e-10 * scale, f"system {s}"
         assert abs(E[s] - Er) <= 1e-12 * abs(Er)
         assert abs(W[s] - Wr) <= 1e-12 * abs(Wr)
@@ -116,7 +116,7 @@ def test_batch_mixed_forces(lj, ctx, oracle, layout):
     for s, sy in enumerate(systems):
         rp, col = oracle.cell_pairs(sy.pos, sy.box, sy.rc + sy.skin)
         Fr, Er, Wr, nr = oracle.forces(sy.pos, sy.box, 1.0, 1.0, sy.rc, rp, col)
-        scale = max(np.abs(Fr).max(), 24.0)
+        scale = np.abs(Fr).max()
         assert np.abs(f[off[s]:off[s + 1]] - Fr).max() <= 1e-5 * scale, f"system {s}"
         # FP32 pair terms over a few hundred atoms: less averaging than at 4k
         assert abs(E[s] - Er) <= 5e-6 * abs(Er), f"system {s}"
@@ -146,7 +146,7 @@ def test_batch_two_level_reduction(lj, ctx, oracle):
     for s, sy in enumerate(systems):
         rp, col = oracle.cell_pairs(sy.pos, sy.box, sy.rc + sy.skin)
         Fr, Er, Wr, nr = oracle.forces(sy.pos, sy.box, 1.0, 1.0, sy.rc, rp, col)
-        scale = max(np.abs(Fr).max(), 24.0)
+        scale = np.abs(Fr).max()
         assert np.abs(f[off[s]:off[s + 1]] - Fr).max() <= 1e-10 * scale, f"system {s}"
         assert abs(E[s] - Er) <= 1e-12 * abs(Er), f"system {s}"
         assert abs(W[s] - Wr) <= 1e-12 * abs(Wr), f"system {s}"
@@ -167,20 +167,35 @@ def run_batch_nve(lj, ctx, systems, dt, nsteps, every, use_graph, precision=0):
                      log_rows=nsteps + 1, batch=True)
         nve.init()
         nve.run(nsteps, use_graph=use_graph)
-        ctx.sync()
+        stale = False
+        try:
+            ctx.sync()
+        except lj.LJError as e:      # a fixed cadence whose lists went stale: reported
+            if e.status != lj.LJ_E_STALE:
+                raise
+            stale = True
     torch.cuda.synchronize()
-    out = pos.cpu().numpy()[:, :3].copy(), vel.cpu().numpy()[:, :3].copy(), nve.log.cpu().numpy().copy()
+    out = (pos.cpu().numpy()[:, :3].copy(), vel.cpu().numpy()[:, :3].copy(),
+           nve.log.cpu().numpy().copy(), stale)
     nve.free()
     nl.free()
     return out
 
 
-def test_batch_nve_matches_oracle(lj, ctx, oracle):
+@pytest.mark.parametrize("every", [10, 0])
+def test_batch_nve_matches_oracle(lj, ctx, oracle, every):
+    """Each system against its own oracle run.  At a fixed cadence the GPU
+    reports a stale list exactly when some system's oracle log shows an atom
+    moved more than skin/2 at a step between builds; with the displacement
+    rule (every = 0) a step rebuilds every system when any needs it, and each
+    system's pairs inside rc are still the oracle's at every step."""
     systems = small_batch(count=10, seed=11)
     off = offsets(systems)
-    p, v, log = run_batch_nve(lj, ctx, systems, 0.005, 25, 10, use_graph=False)
+    p, v, log, stale = run_batch_nve(lj, ctx, systems, 0.005, 25, every, use_graph=False)
+    any_beyond = False
     for s, sy in enumerate(systems):
-        pr, vr, _, lr = oracle.nve(sy.pos, sy.vel, sy.box, 1.0, 1.0, sy.rc, sy.skin, 0.005, 25, 10)
+        pr, vr, _, lr = oracle.nve(sy.pos, sy.vel, sy.box, 1.0, 1.0, sy.rc, sy.skin, 0.005, 25,
+                                   every)
         d = p[off[s]:off[s + 1]] - pr
         d -= sy.box[0] * np.round(d / sy.box[0])
         assert np.abs(d).max() < 1e-9, f"system {s}"
@@ -189,6 +204,17 @@ def test_batch_nve_matches_oracle(lj, ctx, oracle):
         np.testing.assert_allclose(log[:, s, 1], lr[:, 1], rtol=1e-9)
         np.testing.assert_allclose(log[:, s, 2], lr[:, 2], rtol=1e-9)
         assert np.array_equal(log[:, s, 4], lr[:, 4])
+        if every:
+            assert np.array_equal(log[:, s, 5], lr[:, 5])
+            np.testing.assert_allclose(log[:, s, 3], lr[:, 3], rtol=1e-6, atol=1e-12)
+            between = lr[:, 5] == 0.0
+            any_beyond = any_beyond or bool(np.any(lr[between, 3] > 0.5 * sy.skin))
+    if every:
+        assert stale == any_beyond
+    else:
+        assert not stale
+        # every system rebuilt together, at least once
+        assert np.all(log[:, :, 5] == log[:, :1, 5]) and log[1:, 0, 5].sum() >= 1
 
 
 def test_batch_nve_graph_equals_eager(lj, ctx):

@@ -28,6 +28,16 @@ def ctx(lj):
     c.close()
 
 
+def sync_allow_stale(lj, ctx):
+    """lj_sync, accepting the report of a fixed cadence whose list went stale
+    (the run still computed what that cadence defines)."""
+    try:
+        ctx.sync()
+    except lj.LJError as e:
+        if e.status != lj.LJ_E_STALE:
+            raise
+
+
 def to_dev(a, layout):
     return torch.from_numpy(synth.aos4(a) if layout == 0 else synth.soa(a)).to("cuda")
 
@@ -38,14 +48,14 @@ def from_dev(t, layout):
 
 
 def run_gpu(lj, ctx, s, dt, nsteps, every, kind, layout, precision=0, use_graph=False,
-            per_call=None):
+            per_call=None, trunc=0):
     pos, vel = to_dev(s.pos, layout), to_dev(s.vel, layout)
     force = torch.zeros_like(pos)
     torch.cuda.synchronize()
     with torch.cuda.stream(ctx.stream):
         nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=kind)
         nve = lj.NVE(ctx, pos, vel, force, s.box, 1.0, 1.0, s.rc, nl, dt, every, precision,
-                     log_rows=nsteps + 1)
+                     log_rows=nsteps + 1, trunc=trunc)
         nve.init()
         if per_call is None:
             nve.run(nsteps, use_graph=use_graph)
@@ -55,10 +65,16 @@ def run_gpu(lj, ctx, s, dt, nsteps, every, kind, layout, precision=0, use_graph=
                 k = min(per_call, nsteps - done)
                 nve.run(k, use_graph=use_graph)
                 done += k
-        ctx.sync()
+        stale = False
+        try:
+            ctx.sync()
+        except lj.LJError as e:      # a fixed cadence whose list went stale: reported
+            if e.status != lj.LJ_E_STALE:
+                raise
+            stale = True
     torch.cuda.synchronize()
     out = (from_dev(pos, layout), from_dev(vel, layout), from_dev(force, layout),
-           nve.log.cpu().numpy().copy(), nve.steps)
+           nve.log.cpu().numpy().copy(), nve.steps, stale)
     nve.free()
     nl.free()
     return out
@@ -75,8 +91,10 @@ def test_nve_matches_oracle(lj, ctx, oracle, kind, layout):
     dt, n, every = 0.005, 30, 10
     p_ref, v_ref, f_ref, log_ref = oracle.nve(s.pos, s.vel, s.box, 1.0, 1.0, s.rc, s.skin, dt,
                                               n, every)
-    p, v, f, log, steps = run_gpu(lj, ctx, s, dt, n, every, kind, layout)
+    p, v, f, log, steps, stale = run_gpu(lj, ctx, s, dt, n, every, kind, layout)
     assert steps == n
+    between = log_ref[:, 5] == 0.0
+    assert stale == bool(np.any(log_ref[between, 3] > 0.5 * s.skin))
     d = p - p_ref
     d -= s.box[0] * np.round(d / s.box[0])
     assert np.abs(d).max() < 1e-9
@@ -87,6 +105,196 @@ def test_nve_matches_oracle(lj, ctx, oracle, kind, layout):
     np.testing.assert_allclose(log[:, 2], log_ref[:, 2], rtol=1e-9)      # virial
     np.testing.assert_allclose(log[:, 3], log_ref[:, 3], rtol=1e-6, atol=1e-12)   # displacement
     assert np.array_equal(log[:, 4], log_ref[:, 4])                      # interacting pairs
+    assert np.array_equal(log[:, 5], log_ref[:, 5])                      # rebuilt at the step
+
+
+def hot_state():
+    """864 atoms at rho = 0.8, T = 4: the fastest atoms pass skin/2 within a
+    few steps, so a fixed cadence of 10 misses pairs (the oracle's pins show
+    it) and the displacement rule rebuilds several times."""
+    return synth.small_fcc(6, 0.8, 0.05, 41, rc=2.5, T=4.0)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("layout", [0, 1])
+def test_nve_displacement_trigger_matches_oracle(lj, ctx, oracle, kind, layout):
+    """rebuild_every = 0: the list is rebuilt at exactly the oracle's steps
+    (the first at which some atom has moved more than skin/2 since the last
+    build), and the pairs inside rc are the oracle's at every step."""
+    s = hot_state()
+    dt, n = 0.005, 30
+    p_ref, v_ref, f_ref, log_ref = oracle.nve(s.pos, s.vel, s.box, 1.0, 1.0, s.rc, s.skin, dt,
+                                              n, 0)
+    assert log_ref[1:, 5].sum() >= 3
+    p, v, f, log, steps, stale = run_gpu(lj, ctx, s, dt, n, 0, kind, layout)
+    assert steps == n and not stale
+    assert np.array_equal(log[:, 5], log_ref[:, 5])
+    assert np.array_equal(log[:, 4], log_ref[:, 4])
+    np.testing.assert_allclose(log[:, 3], log_ref[:, 3], rtol=1e-6, atol=1e-12)
+    d = p - p_ref
+    d -= s.box[0] * np.round(d / s.box[0])
+    assert np.abs(d).max() < 1e-9
+    assert np.abs(v - v_ref).max() < 1e-8 * np.abs(v_ref).max()
+    np.testing.assert_allclose(log[:, :3], log_ref[:, :3], rtol=1e-9)
+
+
+def test_nve_displacement_trigger_graph_equals_eager(lj, ctx):
+    s = hot_state()
+    a = run_gpu(lj, ctx, s, 0.005, 43, 0, 1, 0, use_graph=False)
+    b = run_gpu(lj, ctx, s, 0.005, 43, 0, 1, 0, use_graph=True)
+    for x, y in zip(a[:4], b[:4]):
+        assert np.array_equal(x, y)
+    assert a[3][1:, 5].sum() >= 3
+
+
+def test_nve_fixed_cadence_reports_stale(lj, ctx, oracle):
+    """The hot system at a fixed cadence of 10: lj_sync reports LJ_E_STALE
+    (some atom moved more than skin/2 between builds), and the run has still
+    computed what the fixed cadence defines: the oracle's pair counts, with
+    the same missing pairs."""
+    s = hot_state()
+    n = 20
+    _, _, _, log_ref = oracle.nve(s.pos, s.vel, s.box, 1.0, 1.0, s.rc, s.skin, 0.005, n, 10)
+    pos, vel = to_dev(s.pos, 0), to_dev(s.vel, 0)
+    force = torch.zeros_like(pos)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(ctx.stream):
+        nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=1)
+        nve = lj.NVE(ctx, pos, vel, force, s.box, 1.0, 1.0, s.rc, nl, 0.005, 10,
+                     log_rows=n + 1)
+        nve.init()
+        nve.run(n)
+        with pytest.raises(lj.LJError) as e:
+            ctx.sync()
+        assert e.value.status == lj.LJ_E_STALE
+        ctx.sync()                          # reported once
+    log = nve.log.cpu().numpy()
+    assert np.array_equal(log[:, 4], log_ref[:, 4])
+    assert np.array_equal(log[:, 5], log_ref[:, 5])
+    assert log[:, 3].max() > 0.5 * s.skin
+    assert nve.steps == n
+    nve.free()
+    nl.free()
+
+
+def inflow_state(c=12.0):
+    """864 atoms of a dilute FCC lattice (rho = 0.074) moving towards the
+    box centre with v = -c (x - L/2): the cloud contracts, so a list rebuilt
+    after a few steps has rows longer than the capacity sized at the start."""
+    s = synth.small_fcc(6, 0.074, 0.0, 7, rc=2.5)
+    s.vel = -c * (s.pos - 0.5 * s.box)
+    return s
+
+
+def run_until(lj, ctx, s, kind, every, nsteps):
+    """(pos, vel, force, log, device step count, error status of lj_sync)."""
+    pos, vel = to_dev(s.pos, 0), to_dev(s.vel, 0)
+    force = torch.zeros_like(pos)
+    torch.cuda.synchronize()
+    status = 0
+    with torch.cuda.stream(ctx.stream):
+        nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=kind)
+        nve = lj.NVE(ctx, pos, vel, force, s.box, 1.0, 1.0, s.rc, nl, 0.005, every,
+                     log_rows=nsteps + 1)
+        nve.init()
+        nve.run(nsteps)
+        try:
+            ctx.sync()
+        except lj.LJError as e:
+            status = e.status
+        steps = nve.steps
+    torch.cuda.synchronize()
+    out = (pos.cpu().numpy().copy(), vel.cpu().numpy().copy(), force.cpu().numpy().copy(),
+           nve.log.cpu().numpy().copy(), steps, status)
+    nve.free()
+    nl.free()
+    return out
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+@pytest.mark.parametrize("every", [10, 0])
+def test_nve_overflow_stops_at_last_good_step(lj, ctx, kind, every):
+    """A rebuild inside a run whose rows outgrow the list's capacity: lj_sync
+    reports LJ_E_CAPACITY, and pos, vel and force are those of the last good
+    step, bit for bit those of a run that stops there; the later log rows
+    are never written."""
+    s = inflow_state()
+    p, v, f, log, good, status = run_until(lj, ctx, s, kind, every, 12)
+    assert status == lj.LJ_E_CAPACITY
+    assert 0 < good < 12
+    assert np.all(log[good + 1:] == 0.0) and np.all(log[good, :3] != 0.0)
+    pr, vr, fr, logr, steps_r, status_r = run_until(lj, ctx, s, kind, every, good)
+    assert steps_r == good and status_r in (0, lj.LJ_E_STALE)
+    if kind == 1:
+        assert np.array_equal(p, pr) and np.array_equal(v, vr) and np.array_equal(f, fr)
+        assert np.array_equal(log[:good + 1], logr[:good + 1])
+    else:
+        # a half list sums its forces with atomics in no fixed order: to rounding
+        for x, y in ((p, pr), (v, vr), (f, fr), (log[:good + 1], logr[:good + 1])):
+            np.testing.assert_allclose(x, y, rtol=1e-11, atol=1e-11 * np.abs(y).max())
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_nve_force_shifted_matches_oracle(lj, ctx, oracle, kind):
+    s = state()
+    dt, n = 0.005, 30
+    p_ref, v_ref, f_ref, log_ref = oracle.nve(s.pos, s.vel, s.box, 1.0, 1.0, s.rc, s.skin, dt,
+                                              n, 10, trunc=1)
+    p, v, f, log, steps, _ = run_gpu(lj, ctx, s, dt, n, 10, kind, 0, trunc=1)
+    d = p - p_ref
+    d -= s.box[0] * np.round(d / s.box[0])
+    assert np.abs(d).max() < 1e-9
+    assert np.abs(v - v_ref).max() < 1e-8
+    np.testing.assert_allclose(log[:, :3], log_ref[:, :3], rtol=1e-9)
+    assert np.array_equal(log[:, 4], log_ref[:, 4])
+
+
+def test_nve_kicks_folded_or_separate_agree_bitwise(lj, ctx):
+    """Full list, fixed cadence: the kicks folded into the force pass (the
+    default) and kept in separate kernels give the same positions and
+    velocities bit for bit; the logged kinetic energy is summed in another
+    order (to rounding)."""
+    s = state()
+    a = run_gpu(lj, ctx, s, 0.005, 27, 10, 1, 0)
+    ctx.tune_set(lj.LJ_TUNE_KICK, 2)
+    try:
+        b = run_gpu(lj, ctx, s, 0.005, 27, 10, 1, 0)
+    finally:
+        ctx.tune_set(lj.LJ_TUNE_KICK, 0)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+    la, lb = a[3], b[3]
+    assert np.array_equal(la[:, [0, 2, 3, 4, 5]], lb[:, [0, 2, 3, 4, 5]])
+    np.testing.assert_allclose(la[:, 1], lb[:, 1], rtol=1e-14)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_nve_aos8_records_equal_aos4(lj, ctx, precision):
+    """Packed (x, y, z, pad, vx, vy, vz, pad) records give the trajectory of
+    separate position and velocity arrays, bit for bit (full list)."""
+    s = state()
+    kind = 1
+    ref = run_gpu(lj, ctx, s, 0.005, 25, 10, kind, 0, precision=precision)
+    rec = np.zeros((s.n, 8))
+    rec[:, :3] = s.pos
+    rec[:, 4:7] = s.vel
+    st = torch.from_numpy(rec).to("cuda")
+    force = torch.zeros((s.n, 4), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    with torch.cuda.stream(ctx.stream):
+        nl = lj.lj_build_neighbors(ctx, st, s.box, s.rc, s.skin, kind=kind)
+        nve = lj.NVE(ctx, st, None, force, s.box, 1.0, 1.0, s.rc, nl, 0.005, 10, precision,
+                     log_rows=26)
+        nve.init()
+        nve.run(25, use_graph=True)
+        sync_allow_stale(lj, ctx)
+    torch.cuda.synchronize()
+    out = st.cpu().numpy()
+    assert np.array_equal(out[:, :3], ref[0]) and np.array_equal(out[:, 4:7], ref[1])
+    assert np.array_equal(force.cpu().numpy()[:, :3], ref[2])
+    assert np.array_equal(nve.log.cpu().numpy(), ref[3])
+    nve.free()
+    nl.free()
 
 
 def test_nve_graph_equals_eager(lj, ctx):
@@ -132,7 +340,7 @@ def test_nve_mixed_forces_match_a_fresh_evaluation(lj, ctx, layout, kind):
         nve.init()
         nve.run(15)
         F, E, W, n = lj.lj_forces(ctx, pos, s.box, 1.0, 1.0, s.rc, nl, lj.LJ_MIXED)
-        ctx.sync()
+        sync_allow_stale(lj, ctx)
     torch.cuda.synchronize()
     log = nve.log.cpu().numpy()
     if kind == 1:
@@ -165,7 +373,7 @@ def test_nve_log_sums_many_row_blocks(lj, ctx):
         nve.init()
         nve.run(3)
         F, E, W, n = lj.lj_forces(ctx, pos, s.box, 1.0, 1.0, s.rc, nl)
-        ctx.sync()
+        sync_allow_stale(lj, ctx)
     torch.cuda.synchronize()
     log = nve.log.cpu().numpy()
     v = from_dev(vel, 0)
@@ -190,7 +398,7 @@ def test_nve_graph_replays_repeatedly(lj, ctx):
         nve.init()
         for _ in range(5):
             nve.run(10, use_graph=True)
-            ctx.sync()
+            sync_allow_stale(lj, ctx)
             _ = (pos.sum() + 1.0).item()      # the program's own eager work between replays
     torch.cuda.synchronize()
     assert np.array_equal(from_dev(pos, 0), ref[0])
@@ -202,8 +410,8 @@ def test_nve_graph_replays_repeatedly(lj, ctx):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_nve_energy_conservation(lj, ctx, precision):
     s = state()
-    _, _, _, log, _ = run_gpu(lj, ctx, s, 0.005, 1000, 10, 1, 0, precision=precision,
-                              use_graph=True)
+    _, _, _, log, _, _ = run_gpu(lj, ctx, s, 0.005, 1000, 10, 1, 0, precision=precision,
+                                 use_graph=True)
     etot = log[:, 0] + log[:, 1]
     assert np.all(np.isfinite(etot))
     assert abs(etot[-1] - etot[0]) < 2e-3 * abs(etot[0])
