@@ -247,6 +247,25 @@ LJ_API lj_status lj_forces(lj_ctx* ctx, const double* pos, int64_t n, int32_t la
                     const lj_list* list, int32_t precision, int32_t trunc, double* force,
                     double* energy, double* virial, int64_t* npairs);
 
+/* lj_forces for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, results and kernels, but the per-block energy/virial
+ * partials live in a static device array of the library (131,072 records of
+ * 32 bytes, 4 MiB, on each GPU it runs on, held until the process ends)
+ * instead of the context's buffer, and the call allocates nothing.
+ * LJ_E_CAPACITY if the list needs more partials than that (about 4M atoms
+ * at 8 lanes per row); LJ_E_INVALID for LJ_MIXED before the list's
+ * fixed-point buffer exists (lj_forces creates it on its first mixed call).
+ * Every call on one GPU shares that array: calls that overlap on a GPU (two
+ * streams or contexts) race and must be ordered by the caller.  The first
+ * call with new eps, sigma, rc or truncation uploads them (synchronously);
+ * with the profiler on, timing events are created. */
+LJ_API lj_status lj_forces_noalloc(lj_ctx* ctx, const double* pos, int64_t n, int32_t layout,
+                                   const double box[3], double eps, double sigma, double rc,
+                                   const lj_list* list, int32_t precision, int32_t trunc,
+                                   double* force, double* energy, double* virial,
+                                   int64_t* npairs);
+
 /* ----------------------------------------------------------------- batches */
 
 /* Many independent systems of uneven size handled by every launch together

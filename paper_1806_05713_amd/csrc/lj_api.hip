@@ -532,8 +532,10 @@ extern "C" lj_status lj_create(int device, void* stream, lj_ctx** out) {
         return st;
     }
     ctx->partials_cap = 4096;
-    if ((st = dmalloc(&ctx->partials, 4 * ctx->partials_cap))) {
+    if ((st = dmalloc(&ctx->partials, 4 * ctx->partials_cap)) ||
+        (st = lj_scratch_partials(device, &ctx->scratch))) {
         dfree(ctx->st);
+        dfree(ctx->partials);
         delete ctx;
         return st;
     }
@@ -886,6 +888,42 @@ extern "C" lj_status lj_forces(lj_ctx* ctx, const double* pos, int64_t n, int32_
     if (precision == LJ_MIXED && (st = lj_list_ensure_q32(l))) return st;
     lj_force_opts o;
     o.trunc = trunc;
+    return lj_launch_forces(ctx, pos, layout, precision, l, l->fc, force, energy, virial, npairs,
+                            o);
+}
+
+extern "C" lj_status lj_forces_noalloc(lj_ctx* ctx, const double* pos, int64_t n,
+                                       int32_t layout, const double box[3], double eps,
+                                       double sigma, double rc, const lj_list* list,
+                                       int32_t precision, int32_t trunc, double* force,
+                                       double* energy, double* virial, int64_t* npairs) {
+    lj_status st = check_common(ctx, pos, n, layout);
+    if (st) return st;
+    if (!list || !force || !energy || !virial)
+        return lj_fail(LJ_E_INVALID, "list, force, energy or virial is NULL");
+    if ((st = check_force_out(layout, force)) || (st = check_trunc(trunc))) return st;
+    if (precision != LJ_FP64 && precision != LJ_MIXED)
+        return lj_fail(LJ_E_INVALID, "unknown precision");
+    if (!box) return lj_fail(LJ_E_INVALID, "box is NULL");
+    if (list->nsys != 1) return lj_fail(LJ_E_INVALID, "a batch list needs lj_forces_batch");
+    if (list->n != n) return lj_fail(LJ_E_STALE, "list was built for another atom count");
+    for (int d = 0; d < 3; ++d)
+        if (list->hsys[0].box[d] != box[d]) return lj_fail(LJ_E_STALE, "list was built for another box");
+    if ((st = check_params(1, &eps, &sigma, &rc, list))) return st;
+    if (lj_force_partials(list) > LJ_SCRATCH_RECORDS)
+        return lj_fail(LJ_E_CAPACITY, "the list needs more block partials than the static "
+                                      "scratch holds (131,072 records: about 4M atoms at 8 "
+                                      "lanes per row); use lj_forces");
+    if (precision == LJ_MIXED && !list->q32)
+        return lj_fail(LJ_E_INVALID, "mixed precision needs the list's fixed-point buffer, "
+                                     "which lj_forces allocates on its first mixed call");
+    DeviceGuard guard(ctx->device);
+    lj_list* l = const_cast<lj_list*>(list);
+    if ((st = set_fconst(ctx, l, &eps, &sigma, &rc, trunc))) return st;
+    lj_force_opts o;
+    o.trunc = trunc;
+    o.partials = ctx->scratch;
+    o.partials_cap = LJ_SCRATCH_RECORDS;
     return lj_launch_forces(ctx, pos, layout, precision, l, l->fc, force, energy, virial, npairs,
                             o);
 }

@@ -30,6 +30,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "lj_force_loop.h"
 #include "lj_internal.h"
@@ -269,6 +270,35 @@ lj_status launch_u(lj_ctx* ctx, const ForceArgs& a, bool half, int layout, int p
 }
 
 }  // namespace
+
+// Block partials of lj_forces_noalloc: device memory of the library itself,
+// one copy per GPU (each device holds its own instance of a __device__
+// array), so that the call allocates nothing.  Host code must not pass the
+// array's name to a kernel (in host code it is a stand-in, not a device
+// address): the address is resolved once per device with
+// hipGetSymbolAddress.  Every force launch writes every record it later
+// reads, so nothing has to be cleared between calls.
+static __device__ __align__(256) double4 scratch[LJ_SCRATCH_RECORDS];
+
+lj_status lj_scratch_partials(int device, double** ptr) {
+    static std::mutex mu;
+    static double* addr[LJ_MAX_DEVICES] = {};
+    if (device < 0 || device >= LJ_MAX_DEVICES)
+        return lj_fail(LJ_E_INVALID, "device index beyond the library's table");
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        int prev = -1;
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        hipError_t e = hipSetDevice(device);
+        void* p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (prev >= 0 && prev != device) (void)hipSetDevice(prev);
+        if (e != hipSuccess) return lj_hip_fail(e, "hipGetSymbolAddress(scratch)");
+        addr[device] = static_cast<double*>(p);
+    }
+    *ptr = addr[device];
+    return LJ_OK;
+}
 
 int64_t lj_force_blocks(int64_t nslices) {
     return (nslices + LJ_WAVES_PER_BLOCK - 1) / LJ_WAVES_PER_BLOCK;

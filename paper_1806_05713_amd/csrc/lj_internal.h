@@ -117,6 +117,7 @@ struct lj_ctx {
     lj_dev_status* st;             // device
     double* partials;              // device, per-block E/W/count partials
     int64_t partials_cap;          // in blocks
+    double* scratch;               // the device's static partials (lj_forces_noalloc)
     bool prof_on;
     std::vector<lj_prof_rec> prof;
     int32_t tune[LJ_TUNE_N];       // tuning knobs (lj_tune_set)
@@ -217,6 +218,12 @@ int64_t lj_force_blocks(int64_t nslices);
 // (double4) the context must hold for list l.
 int lj_force_split(const lj_list* l);
 int64_t lj_force_partials(const lj_list* l);
+// lj_forces_noalloc: block partials in a static device array of
+// LJ_SCRATCH_RECORDS double4 records (4 MiB) per GPU; its device address
+// on `device` (resolved once per device, then cached).
+#define LJ_SCRATCH_RECORDS (1 << 17)
+#define LJ_MAX_DEVICES 64
+lj_status lj_scratch_partials(int device, double** ptr);
 // Momentum update folded into the force pass (the impulse form of Alg. 1),
 // full lists only: once a row's force F is summed, its atom's velocity is
 // kicked in place.

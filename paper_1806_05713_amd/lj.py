@@ -38,7 +38,8 @@ EXPORTS = ["lj_create", "lj_destroy", "lj_set_stream", "lj_sync", "lj_build_cell
            "lj_list_device_view", "lj_forces", "lj_nve_create", "lj_nve_init", "lj_nve_run",
            "lj_nve_steps", "lj_nve_free", "lj_build_neighbors_batch", "lj_forces_batch",
            "lj_list_sys_info", "lj_nve_create_batch",
-           "lj_profile_begin", "lj_profile_end", "lj_tune_set", "lj_tune_get", "lj_last_error"]
+           "lj_profile_begin", "lj_profile_end", "lj_tune_set", "lj_tune_get", "lj_last_error",
+           "lj_forces_noalloc"]
 LJ_TUNE_BUILD_LANES, LJ_TUNE_FORCE_BATCH, LJ_TUNE_CELL_DIV, LJ_TUNE_KICK, LJ_TUNE_N = 0, 1, 2, 3, 4
 LJ_PROF_CELLS, LJ_PROF_NEIGH, LJ_PROF_FORCE, LJ_PROF_OTHER, LJ_PROF_INTEGRATE = 0, 1, 2, 3, 4
 LJ_PROF_N = 5
@@ -102,6 +103,8 @@ def load(path: str = LIB_PATH):
         "lj_list_device_view": ([_VP, ctypes.POINTER(ListView)]),
         "lj_forces": ([_VP, _VP, i64, i32, _D3, dbl, dbl, dbl, _VP, i32, i32, _VP, _VP, _VP,
                        _VP]),
+        "lj_forces_noalloc": ([_VP, _VP, i64, i32, _D3, dbl, dbl, dbl, _VP, i32, i32, _VP, _VP,
+                               _VP, _VP]),
         "lj_nve_create": ([_VP, _VP, _VP, _VP, i64, i32, _D3, dbl, dbl, dbl, i32, i32, _VP, dbl,
                            i32, _VP, i64, PP]),
         "lj_nve_create_batch": ([_VP, _VP, _VP, _VP, i32, _VP, _VP, _VP, i32, i32, _VP, dbl,
@@ -341,6 +344,19 @@ def lj_forces(ctx: Context, pos, box, eps: float, sigma: float, rc: float,
                             float(rc), nlist.h, int(precision), int(trunc), _ptr(force),
                             _ptr(out), out.data_ptr() + 8, _ptr(cnt)), "lj_forces")
     return force, out[0:1], out[1:2], cnt
+
+
+def lj_forces_noalloc(ctx: Context, pos, box, eps: float, sigma: float, rc: float,
+                      nlist: NeighborList, precision: int, force, energy, virial, npairs,
+                      trunc: int = LJ_TRUNC_SHIFT):
+    """lj_forces with the library's static block partials: every output is a
+    caller-allocated device tensor (force like pos, energy / virial float64
+    of 1, npairs int64 of 1); nothing is allocated here."""
+    n, layout = _pos_layout(pos)
+    _check(load().lj_forces_noalloc(ctx.h, _ptr(pos), n, layout, _box(box), float(eps),
+                                    float(sigma), float(rc), nlist.h, int(precision), int(trunc),
+                                    _ptr(force), _ptr(energy), _ptr(virial), _ptr(npairs)),
+           "lj_forces_noalloc")
 
 
 def _harr(a, dtype):
