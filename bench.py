@@ -1,23 +1,31 @@
 #!/usr/bin/env python3
 """Benchmark of the LJ Verlet-list path on one MI355X.
 
-One step = one pass of the whole hot path over one synthetic system held in
-HBM: validate and bin the positions into cells, sort them by cell, rebuild
-the Verlet list in place, then compute forces, potential energy and virial
-(lj_update_neighbors + lj_forces).  The workload is the 131,072-atom FCC
+Headline (the paper's measurement, Sec. II: the time of the force
+evaluations, the list built once): one step = one evaluation of forces,
+potential energy and virial over the Verlet list (lj_forces: the force
+kernel and the fixed-order energy/virial reduction) on the 131,072-atom FCC
 fluid at rho = 1.0, rc = 3.0, skin = 0.3 (32^3 unit cells, jitter +-0.1),
-FP64, positions as padded double4 records, atoms cell-sorted (cubic cells of
-side >= rc + skin, z-major; `--order lattice | permuted` for the others).
+FP64, full list, positions as padded double4 records, atoms cell-sorted
+(`--order lattice | permuted` for the others).  `value` = interacting pairs
+(r < rc, each unordered pair once) per second of such steps, timed with HIP
+events on the library's stream over exactly K steps.
 
-Prints ONE JSON line.  `value` = interacting pairs (r < rc, each unordered
-pair once) per second of whole steps.  Extra keys: per-kernel times from HIP
-events on the library's stream, the roofline of the dominant kernel, the
-force-kernel-only rate (what the paper times), the variant matrix (atom order
-x layout x list kind x precision) and the CPU oracle baseline.
+Prints ONE JSON line.  Besides the contract keys: the roofline of the force
+kernel (its algorithmic bytes over its mean launch time, from the library's
+HIP-event profiler, against 8 TB/s), its HBM traffic, L2 hit rate and VALU
+issue utilisation from the committed rocprofv3 counter summary while the
+kernel sources are unchanged since the counters were taken; the whole hot
+path per step (cell binning + list rebuild + forces) with the list build's
+own roofline; mixed precision, half list, force-shifted truncation and
+64-byte records; the order x layout x list x precision matrix; the 4M-atom
+NVE run and the 512-system batch (short forms); and the oracle baseline
+(its force evaluation, one thread and all host cores).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import platform
@@ -30,14 +38,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
-FP64_VECTOR_TFLOPS = 78.6  # MI355X FP64 vector peak (fused multiply-adds counted as 2)
-# Vector operations per second without fusion, FP64 or unpacked FP32: 256 CUs
-# x 4 SIMDs x 16 lanes x 2.4 GHz.  The pair test forms r^2 from separately
-# rounded products and sums, so no multiply-add can be fused and this is its
-# ceiling.
-VALU_OPS_PEAK_T = 256 * 4 * 16 * 2.4e9 / 1e12
-TEST_OPS = 8               # per candidate pair test: 3 differences, 3 squares, 2 sums
+# The list build's pair test runs in FP32 (FMA-contracted) on unpacked
+# instructions (packed FP32 is disabled in this build), so its ceiling is
+# 256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s, half the
+# published packed FP32 vector peak of 157.3.
+FP32_UNPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+TEST_FLOPS = 8             # per candidate pair test: 3 differences, 3 squares, 2 sums
 COPY_BYTES = 256 << 20     # size of the calibration copy (read once, written once)
+SIMDS = 256 * 4
+CLOCK_GHZ = 2.4
 
 
 def algorithmic_force_bytes(n: int, entries: int) -> int:
@@ -47,16 +56,11 @@ def algorithmic_force_bytes(n: int, entries: int) -> int:
     return n * (32 + 32 + 8) + 4 * entries
 
 
-def traffic_file(kernel: str) -> str:
-    return os.path.join(ROOT, "profiles", f"{kernel}_lj131k_hbm_traffic.txt")
-
-
-def measured_traffic(path: str):
-    """HBM bytes per force launch from the committed counter summary (two
-    rocprofv3 --pmc passes, FETCH_SIZE and WRITE_SIZE, scaled by a plain copy),
-    or None when the summary is missing or the force-kernel sources have
-    changed since the counters were taken."""
-    import hashlib
+def profile_summary(name: str):
+    """Key/value lines of a committed rocprofv3 summary under profiles/, or
+    None when it is missing or the sources it names have changed since the
+    counters were taken (then its figures no longer describe the kernel)."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -72,9 +76,22 @@ def measured_traffic(path: str):
                 h.update(f.read())
         if h.hexdigest() != kv["source_sha256"]:
             return None
-        return int(kv["traffic_bytes_per_launch"])
-    except (KeyError, OSError, ValueError):
+    except (KeyError, OSError):
         return None
+    return kv
+
+
+def counters(name: str, keys):
+    kv = profile_summary(name)
+    if kv is None:
+        return None
+    out = {"source": f"profiles/{name}"}
+    for k in keys:
+        try:
+            out[k] = float(kv[k].split()[0])
+        except (KeyError, ValueError, IndexError):
+            out[k] = None
+    return out
 
 
 def ordered(s, order: str):
@@ -88,6 +105,9 @@ def ordered(s, order: str):
 
 
 def time_steps(torch, fn, steps: int, warmup: int):
+    """ms per call of fn over exactly `steps` calls after `warmup`, from HIP
+    events on the current stream (the library's), with a synchronisation on
+    both sides; also the wall-clock ms per call."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
@@ -103,28 +123,73 @@ def time_steps(torch, fn, steps: int, warmup: int):
     return a.elapsed_time(b) / steps, wall / steps * 1e3
 
 
-def cpu_baseline(sys_, budget_s: float = 20.0):
-    """The oracle (scalar FP64 C, one thread) on the same workload: one step =
-    linked-list cell search + counting sort + force loop.  Repeats whole steps
-    until about budget_s of CPU time is used (at least one)."""
+def per_launch(ctx, fn, steps: int):
+    """us per launch of each phase over `steps` calls of fn (the library's
+    HIP-event profiler on its stream)."""
+    ctx.profile_begin()
+    for _ in range(steps):
+        fn()
+    prof = ctx.profile_end()
+    return {k: (v[0] / max(v[1], 1) * 1e3) for k, v in prof.items()}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(s, single_budget_s: float = 10.0, multi_budget_s: float = 6.0):
+    """The oracle (scalar FP64 C, -O2 without contraction) timed on this
+    host: its force evaluation over the full list (built once by its own
+    cell list, not timed), as the paper times the force calls alone; one
+    thread, and all host cores (an OpenMP loop over rows whose result is
+    bitwise that of one thread).  Each leg repeats whole evaluations until
+    its budget is used; the median is reported."""
     from oracle.ljref import Oracle
     O = Oracle()
-    rs = sys_.rc + sys_.skin
-    times, nin = [], 0
-    t_start = time.perf_counter()
-    while True:
-        t0 = time.perf_counter()
-        rp, col = O.cell_pairs(sys_.pos, sys_.box, rs)
-        F, E, W, nin = O.forces(sys_.pos, sys_.box, 1.0, 1.0, sys_.rc, rp, col)
-        times.append(time.perf_counter() - t0)
-        if time.perf_counter() - t_start > budget_s or len(times) >= 20:
-            break
-    t = float(np.median(times))
-    return {"value": nin / t, "unit": "pair interactions/s", "cores": 1, "kind": "oracle",
-            "sample": f"{len(times)} whole steps (cell list build + forces, {sys_.n} atoms, "
-                      f"{nin} interacting pairs), median {t:.3f} s/step, single thread, "
-                      f"host {platform.processor() or platform.machine()}, "
-                      f"{os.cpu_count()} logical CPUs present"}
+    rp, col = O.cell_pairs(s.pos, s.box, s.rc + s.skin)
+    frp, fcol = O.full_pairs(rp, col)
+    legs = {}
+    ref = None
+    for name, threads in (("single", 1), ("all", 0)):
+        was = O.set_threads(0)
+        # all cores: the host's share for this process (OMP_NUM_THREADS when set)
+        n_all = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or os.cpu_count() or 1
+        used = O.set_threads(threads if threads else n_all)
+        times = []
+        t_start = time.perf_counter()
+        budget = single_budget_s if threads == 1 else multi_budget_s
+        while True:
+            t0 = time.perf_counter()
+            F, E, W, nin = O.forces_full(s.pos, s.box, 1.0, 1.0, s.rc, frp, fcol)
+            times.append(time.perf_counter() - t0)
+            if time.perf_counter() - t_start > budget or len(times) >= 200:
+                break
+        O.set_threads(was)
+        if ref is None:
+            ref = (F, E, W)
+        else:
+            legs["bitwise_equal_to_single_thread"] = bool(
+                np.array_equal(F, ref[0]) and E == ref[1] and W == ref[2])
+        t = float(np.median(times))
+        legs[name] = {"threads": used, "evaluations": len(times), "s_per_eval": round(t, 5),
+                      "pairs_per_s": round(nin / t, 1)}
+    return {"value": legs["all"]["pairs_per_s"], "unit": "pair interactions/s",
+            "cores": legs["all"]["threads"], "kind": "oracle",
+            "sample": f"{legs['all']['evaluations']} force evaluations of the oracle over the "
+                      f"full list ({s.n} atoms, {nin} interacting pairs; list built once, not "
+                      f"timed), OpenMP over rows on {legs['all']['threads']} threads, median "
+                      f"{legs['all']['s_per_eval']} s each; host {cpu_model()}, nproc "
+                      f"{os.cpu_count()}",
+            "single_thread": legs["single"], "all_cores": legs["all"],
+            "bitwise_equal_to_single_thread": legs["bitwise_equal_to_single_thread"],
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
 
 
 def main():
@@ -135,23 +200,32 @@ def main():
     ap.add_argument("--kind", choices=["full", "half"], default="full")
     ap.add_argument("--order", choices=["cellsorted", "lattice", "permuted"],
                     default="cellsorted", help="atom order of the input")
-    ap.add_argument("--lanes", type=int, default=0, help="lanes per list row (0: default)")
+    ap.add_argument("--lanes", type=int, default=0,
+                    help="lanes per list row (0: the tuned or default choice)")
     ap.add_argument("--build-lanes", type=int, default=0,
                     help="lanes per row in the list build, 64, 1, 2 or 4 (0: default, 64)")
     ap.add_argument("--force-batch", type=int, default=0,
                     help="list entries in flight per lane in the force kernel, 2, 4 or 8 "
                          "(0: default)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-variants", action="store_true", help="skip the variant matrix")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the variant matrix and the 4M / batch workloads")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="the headline only (no whole step, other forms, variants, 4M or "
+                         "batch workloads): the command the force kernel's counters are "
+                         "taken with")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three plain 256 MiB device-to-device copies (a known-size "
                          "kernel that scales HBM byte counters)")
     ap.add_argument("--workload", choices=["lj131k", "lj4m", "batch512", "accuracy"],
                     default="lj131k",
-                    help="lj131k (default): build + forces on the 131k-atom fluid; lj4m: "
-                         "100-step NVE of the 4M-atom fluid; batch512: 100-step NVE of 512 "
-                         "batched systems; accuracy: 10,000-step mixed vs FP64 run on the "
-                         "500k-atom fluid (use --steps to shorten)")
+                    help="lj131k (default): the headline and its extras; lj4m: the 4M-atom "
+                         "NVE runs alone; batch512: the batched NVE alone (--tune to retune "
+                         "its launch shapes into the cache); accuracy: 10,000-step mixed vs "
+                         "FP64 run on the 500k-atom fluid (use --steps to shorten)")
+    ap.add_argument("--tune", action="store_true",
+                    help="retune launch shapes (131k headline or batch512) and save them in "
+                         "the autotuner's cache")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the "
@@ -160,7 +234,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1806_05713_amd import lj, synth
+    from paper_1806_05713_amd import autotune, lj, synth, workloads
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
@@ -173,35 +247,51 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.workload != "lj131k":
-        from paper_1806_05713_amd import workloads
         if args.workload == "accuracy":
             result = workloads.accuracy_lj500k(steps=args.steps)
+        elif args.workload == "lj4m":
+            result = workloads.bench_lj4m(steps=args.steps, warmup=args.warmup)
         else:
-            fn = workloads.bench_lj4m if args.workload == "lj4m" else workloads.bench_batch512
-            result = fn(steps=args.steps, warmup=args.warmup, cpu=not args.no_cpu)
+            result = workloads.bench_batch512(steps=args.steps, warmup=args.warmup,
+                                              tune=args.tune)
         print(json.dumps(result), flush=True)
         return
-    ctx = lj.Context(0)
-    if args.build_lanes:
-        ctx.tune_set(lj.LJ_TUNE_BUILD_LANES, args.build_lanes)
-    if args.force_batch:
-        ctx.tune_set(lj.LJ_TUNE_FORCE_BATCH, args.force_batch)
 
+    ctx = lj.Context(0)
     s = ordered(synth.lj131k(), args.order)
     kind = lj.LJ_LIST_FULL if args.kind == "full" else lj.LJ_LIST_HALF
     pos = torch.from_numpy(synth.aos4(s.pos)).to(dev)
-    nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=kind, lanes=args.lanes)
+    # launch shapes: given on the command line, else the autotuner's cached
+    # choice for this device and workload shape, else the library's defaults
+    tkey = autotune.system_key(s.n, 1.0, s.rc + s.skin, kind, lj.LJ_FP64)
+    if args.tune:
+        shape = autotune.best_config(ctx, pos, s.box, s.rc, s.skin, kind, lj.LJ_FP64, 1.0,
+                                     objective="force_us", retune=True,
+                                     space={"lanes": (4, 8, 16), "build_lanes": (64,),
+                                            "batch": (2, 4, 8), "cell_div": (2,)},
+                                     log=lambda m: print(f"[tune] {m}", file=sys.stderr))
+        shape_from = "tuned now"
+    else:
+        shape = autotune.cached(tkey)
+        shape_from = "cache" if shape else "defaults"
+    shape = dict(shape or {})
+    if args.lanes:
+        shape["lanes"], shape_from = args.lanes, "command line"
+    if args.build_lanes:
+        shape["build_lanes"], shape_from = args.build_lanes, "command line"
+    if args.force_batch:
+        shape["batch"], shape_from = args.force_batch, "command line"
+    autotune.apply(ctx, shape)
+    nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=kind,
+                               lanes=shape.get("lanes", 0))
     force = torch.empty_like(pos)
     out = torch.empty(2, dtype=torch.float64, device=dev)
+    cnt = torch.empty(1, dtype=torch.int64, device=dev)
 
     def step():
-        lj.lj_update_neighbors(ctx, pos, s.box, nl)
         lj.lj_forces(ctx, pos, s.box, 1.0, 1.0, s.rc, nl, lj.LJ_FP64, force, out)
 
-    def force_only():
-        lj.lj_forces(ctx, pos, s.box, 1.0, 1.0, s.rc, nl, lj.LJ_FP64, force, out)
-
-    # ---- timed region: exactly K whole steps
+    # ---- timed region: exactly K force evaluations over the list built once
     torch.cuda.synchronize()
     ms_step, wall_step = time_steps(torch, step, args.steps, args.warmup)
     ctx.sync()
@@ -211,72 +301,27 @@ def main():
     desc = nl.info()
     value = npairs / (ms_step * 1e-3)
 
-    # ---- per-kernel device times: the same K steps with HIP events around each launch
-    ctx.profile_begin()
-    for _ in range(args.steps):
-        step()
-    prof = ctx.profile_end()
-    per = {k: (v[0] / max(v[1], 1) * 1e3) for k, v in prof.items()}   # us per launch
-    ms_force_only, _ = time_steps(torch, force_only, args.steps, 2)
-
-    # the same whole step with the mixed-precision force kernel (fixed-point
-    # gathers, FP32 pair terms); the pair set is the FP64 one
-    force_m = torch.empty_like(pos)
-
-    def step_mixed():
-        lj.lj_update_neighbors(ctx, pos, s.box, nl)
-        lj.lj_forces(ctx, pos, s.box, 1.0, 1.0, s.rc, nl, lj.LJ_MIXED, force_m, out)
-
-    ms_step_mixed, _ = time_steps(torch, step_mixed, args.steps, args.warmup)
-    ctx.sync()
-
+    # ---- per-kernel device times over the same K evaluations
+    per = per_launch(ctx, step, args.steps)
     force_us = per["force"]
-    neigh_us = per["neigh"]
-    default_shape = (args.order == "cellsorted" and args.lanes in (0, 8) and
-                     args.build_lanes in (0, 64) and
-                     args.force_batch in (0, 4))
     bytes_force = algorithmic_force_bytes(s.n, desc.entries)
     force_gbs = bytes_force / (force_us * 1e-6) / 1e9
-    roofline_force = {
+    default_shape = (args.order == "cellsorted" and kind == lj.LJ_LIST_FULL and
+                     desc.lanes == 8 and shape.get("batch", 4) in (0, 4))
+    cf = counters("k_force_lj131k_counters.txt",
+                  ["traffic_bytes_per_launch", "l2_hit_rate", "valu_issue_utilisation",
+                   "ta_busy", "vmem_instructions_per_launch", "valu_instructions_per_launch",
+                   "duration_us"]) if default_shape else None
+    roofline = {
         "kernel": "k_force (FP64, full list)" if kind == lj.LJ_LIST_FULL
         else "k_force (FP64, half list)",
         "bound": "hbm", "achieved": round(force_gbs, 1), "peak": HBM_PEAK_GBS,
         "unit": "GB/s", "frac": round(force_gbs / HBM_PEAK_GBS, 4),
-        "traffic": measured_traffic(traffic_file("k_force"))
-        if (kind == lj.LJ_LIST_FULL and default_shape) else None,
-        "bytes_per_launch": bytes_force, "us_per_launch": round(force_us, 3)}
-    # the list build: bound by vector-ALU issue; its algorithmic work is the
-    # distance test of every candidate pair it examines (8 operations, unfused:
-    # FP32 first, FP64 again in the narrow band around rs; unpacked FP32 and
-    # FP64 issue at the same rate)
-    neigh_tflops = TEST_OPS * desc.tests / (neigh_us * 1e-6) / 1e12
-    roofline_neigh = {
-        "kernel": "k_neigh_rows (list build, exact pair tests: FP32 with an FP64 band)",
-        "bound": "alu", "achieved": round(neigh_tflops, 3), "peak": round(VALU_OPS_PEAK_T, 2),
-        "unit": "TFLOP/s", "frac": round(neigh_tflops / VALU_OPS_PEAK_T, 4),
-        "traffic": measured_traffic(traffic_file("k_neigh_rows"))
-        if (kind == lj.LJ_LIST_FULL and default_shape) else None,
-        "candidate_tests_per_launch": int(desc.tests), "us_per_launch": round(neigh_us, 3)}
-    dominant = "force" if force_us >= neigh_us else "neigh"
-    roofline = roofline_force if dominant == "force" else roofline_neigh
-
-    variants = {}
-    if not args.no_variants:
-        for order in ("cellsorted", "lattice", "permuted"):
-            sv = ordered(synth.lj131k(), order)
-            for layout_name, layout in (("aos4", 0), ("soa", 1)):
-                p = torch.from_numpy(synth.aos4(sv.pos) if layout == 0 else synth.soa(sv.pos)).to(dev)
-                f = torch.empty_like(p)
-                for kname, kv in (("full", lj.LJ_LIST_FULL), ("half", lj.LJ_LIST_HALF)):
-                    l2 = lj.lj_build_neighbors(ctx, p, sv.box, sv.rc, sv.skin, kind=kv)
-                    for prec_name, prec in (("fp64", lj.LJ_FP64), ("mixed", lj.LJ_MIXED)):
-                        def fo():
-                            lj.lj_forces(ctx, p, sv.box, 1.0, 1.0, sv.rc, l2, prec, f, out)
-                        ms, _ = time_steps(torch, fo, 50, 5)
-                        variants[f"{order}/{layout_name}/{kname}/{prec_name}"] = {
-                            "force_us": round(ms * 1e3, 3),
-                            "pairs_per_s": round(npairs / (ms * 1e-3), 1)}
-                    l2.free()
+        "traffic": int(cf["traffic_bytes_per_launch"]) if cf and cf["traffic_bytes_per_launch"]
+        else None,
+        "bytes_per_launch": bytes_force, "us_per_launch": round(force_us, 3),
+        "pairs_per_s_kernel": round(npairs / (force_us * 1e-6), 1),
+        "counters": cf}
 
     result = {
         "metric": "pair interactions/s (FP64 vs FP32/FP64-mixed) at rho=1, rc=3; HBM GB/s",
@@ -297,27 +342,112 @@ def main():
                                + {"cellsorted": "cell-sorted (cells of side >= rc + skin)",
                                   "lattice": "in lattice order",
                                   "permuted": "in random order"}[args.order]
-                               + "; step = cell binning + list rebuild + forces/energy/virial",
+                               + f", {args.kind} Verlet list built once; step = one force/"
+                               "energy/virial evaluation over the list (the paper times the "
+                               "force calls alone)",
                    "atoms": s.n, "list": args.kind, "lanes": desc.lanes, "layout": "aos4",
-                   "order": args.order, "precision": "fp64",
-                   "list_entries": desc.entries, "candidate_tests": int(desc.tests),
-                   "interacting_pairs": npairs},
+                   "order": args.order, "precision": "fp64", "launch_shapes": shape,
+                   "launch_shapes_from": shape_from,
+                   "list_entries": desc.entries, "interacting_pairs": npairs},
         "kernel_us": {k: round(v, 3) for k, v in per.items()},
-        "dominant_kernel": dominant,
         "roofline": roofline,
-        "roofline_force": roofline_force,
-        "roofline_neigh": roofline_neigh,
-        "mixed_step": {"ms_per_step": round(ms_step_mixed, 6),
-                       "pairs_per_s": round(npairs / (ms_step_mixed * 1e-3), 1),
-                       "speedup_over_fp64": round(ms_step / ms_step_mixed, 3)},
-        "force_only": {"us": round(ms_force_only * 1e3, 3),
-                       "pairs_per_s": round(npairs / (ms_force_only * 1e-3), 1),
-                       "alg_GBps": round(bytes_force / (ms_force_only * 1e-3) / 1e9, 1)},
-        "variants": variants,
     }
+
+    if args.no_extras:
+        if not args.no_cpu:
+            result["cpu_baseline"] = cpu_baseline(s)
+        print(json.dumps(result), flush=True)
+        return
+
+    # ---- the whole hot path per step: bin + sort + rebuild the list in place + forces
+    def whole():
+        lj.lj_update_neighbors(ctx, pos, s.box, nl)
+        lj.lj_forces(ctx, pos, s.box, 1.0, 1.0, s.rc, nl, lj.LJ_FP64, force, out)
+
+    ms_whole, _ = time_steps(torch, whole, args.steps, args.warmup)
+    ctx.sync()
+    per_w = per_launch(ctx, whole, args.steps)
+    desc = nl.info()
+    neigh_tf = TEST_FLOPS * desc.tests / (per_w["neigh"] * 1e-6) / 1e12
+    cb = counters("k_neigh_rows_lj131k_counters.txt",
+                  ["traffic_bytes_per_launch", "l2_hit_rate", "valu_issue_utilisation",
+                   "valu_instructions_per_launch", "duration_us"]) if default_shape else None
+    result["whole_step"] = {
+        "what": "cell binning and sort, list rebuild in place, forces/energy/virial (the whole "
+                "hot path over one input resident in HBM)",
+        "ms_per_step": round(ms_whole, 6),
+        "pairs_per_s": round(npairs / (ms_whole * 1e-3), 1),
+        "kernel_us": {k: round(v, 3) for k, v in per_w.items()},
+        "roofline_build": {"kernel": "k_neigh_rows (list build: FP32 pair test with an FP64 "
+                                     "band, FMA-contracted)",
+                           "bound": "alu", "unit": "TFLOP/s",
+                           "achieved": round(neigh_tf, 3),
+                           "peak": round(FP32_UNPACKED_TFLOPS, 1),
+                           "frac": round(neigh_tf / FP32_UNPACKED_TFLOPS, 4),
+                           "frac_of_published_fp32_157": round(neigh_tf / 157.3, 4),
+                           "candidate_tests_per_launch": int(desc.tests),
+                           "us_per_launch": round(per_w["neigh"], 3),
+                           "counters": cb}}
+
+    # ---- the other forms of the force evaluation (same list kind and atoms)
+    def rate(fn, reps=None):
+        ms, _ = time_steps(torch, fn, reps or args.steps, 3)
+        return {"us": round(ms * 1e3, 3), "pairs_per_s": round(npairs / (ms * 1e-3), 1),
+                "speedup_over_fp64": round(ms_step / ms, 3)}
+
+    lj.lj_update_neighbors(ctx, pos, s.box, nl)
+    ctx.sync()
+    force_m = torch.empty_like(pos)
+    result["mixed"] = {
+        "what": "fixed-point (32-bit, fraction of the box) position gathers, FP64 r^2 and "
+                "exact cutoff test, FP32 pair terms, FP64 accumulation and reductions",
+        **rate(lambda: lj.lj_forces(ctx, pos, s.box, 1.0, 1.0, s.rc, nl, lj.LJ_MIXED, force_m,
+                                    out))}
+    result["force_shifted"] = rate(lambda: lj.lj_forces(ctx, pos, s.box, 1.0, 1.0, s.rc, nl,
+                                                        lj.LJ_FP64, force_m, out, trunc=1))
+    nl_h = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=lj.LJ_LIST_HALF)
+    result["half_list"] = rate(lambda: lj.lj_forces(ctx, pos, s.box, 1.0, 1.0, s.rc, nl_h,
+                                                    lj.LJ_FP64, force_m, out), 20)
+    result["half_list"]["entries"] = nl_h.info().entries
+    nl_h.free()
+    rec = np.zeros((s.n, 8))
+    rec[:, :3] = s.pos
+    pos8 = torch.from_numpy(rec).to(dev)
+    nl8 = lj.lj_build_neighbors(ctx, pos8, s.box, s.rc, s.skin, kind=kind,
+                                lanes=shape.get("lanes", 0))
+    result["aos8_records"] = rate(lambda: lj.lj_forces(ctx, pos8, s.box, 1.0, 1.0, s.rc, nl8,
+                                                       lj.LJ_FP64, force_m, out))
+    nl8.free()
+    del pos8
+
+    if not args.no_variants:
+        variants = {}
+        for order in ("cellsorted", "lattice", "permuted"):
+            sv = ordered(synth.lj131k(), order)
+            for layout_name, layout in (("aos4", 0), ("soa", 1)):
+                p = torch.from_numpy(synth.aos4(sv.pos) if layout == 0 else synth.soa(sv.pos)).to(dev)
+                f = torch.empty_like(p)
+                for kname, kv in (("full", lj.LJ_LIST_FULL), ("half", lj.LJ_LIST_HALF)):
+                    l2 = lj.lj_build_neighbors(ctx, p, sv.box, sv.rc, sv.skin, kind=kv)
+                    for prec_name, prec in (("fp64", lj.LJ_FP64), ("mixed", lj.LJ_MIXED)):
+                        def fo():
+                            lj.lj_forces(ctx, p, sv.box, 1.0, 1.0, sv.rc, l2, prec, f, out)
+                        ms, _ = time_steps(torch, fo, 20, 3)
+                        variants[f"{order}/{layout_name}/{kname}/{prec_name}"] = {
+                            "force_us": round(ms * 1e3, 3),
+                            "pairs_per_s": round(npairs / (ms * 1e-3), 1)}
+                    l2.free()
+        result["variants"] = variants
+        nl.free()
+        ctx.close()
+        del pos, force, force_m
+        torch.cuda.empty_cache()
+        result["lj4m_nve"] = workloads.bench_lj4m(steps=100, warmup=10)
+        torch.cuda.empty_cache()
+        result["batch512_nve"] = workloads.bench_batch512(steps=100, warmup=10)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(s)
-        result["gpu_vs_cpu_oracle"] = round(value / result["cpu_baseline"]["value"], 1)
+        result["gpu_vs_cpu_oracle_all_cores"] = round(value / result["cpu_baseline"]["value"], 1)
     print(json.dumps(result), flush=True)
 
 

@@ -42,6 +42,29 @@ def key(device_name: str, cus: int, n: int, rho: float, rs: float, kind: int,
     return f"{device_name}/{cus}cu/n2^{nb}/rho{rho:.2f}/rs{rs:.2f}/k{kind}/p{precision}"
 
 
+def device_tag() -> str:
+    """Architecture and compute-unit count of cuda:0 (part of every cache key)."""
+    import torch
+    props = torch.cuda.get_device_properties(0)
+    name = getattr(props, "gcnArchName", props.name).split(":")[0]
+    return f"{name}/{props.multi_processor_count}cu"
+
+
+def system_key(n: int, rho: float, rs: float, kind: int, precision: int) -> str:
+    arch, cus = device_tag().split("/")
+    return key(arch, int(cus[:-2]), n, rho, rs, kind, precision)
+
+
+def batch_key(name: str, kind: int, precision: int) -> str:
+    """Cache key of a named batch workload."""
+    return f"{device_tag()}/batch:{name}/k{kind}/p{precision}"
+
+
+def cached(k: str, path: str = CACHE) -> Optional[dict]:
+    """The cached configuration under key k, or None."""
+    return load_cache(path).get(k)
+
+
 def load_cache(path: str = CACHE) -> Dict[str, dict]:
     if os.path.exists(path):
         with open(path) as f:
@@ -161,17 +184,17 @@ def tune_batch(ctx, pos, n, box, rc, skin, kind=lj.LJ_LIST_FULL, precision=lj.LJ
 
 
 def best_config(ctx, pos, box, rc, skin, kind, precision, rho: float,
+                objective: str = "force_us", space: Optional[dict] = None,
                 cache_path: str = CACHE, retune: bool = False, log=None) -> dict:
-    """Cached tuned configuration for this device and workload shape."""
-    import torch
-    props = torch.cuda.get_device_properties(pos.device)
-    k = key(getattr(props, "gcnArchName", props.name), props.multi_processor_count,
-            int(pos.numel() // 4 if pos.dim() == 2 and pos.shape[1] == 4 else pos.shape[1]),
-            rho, rc + skin, kind, precision)
+    """Cached tuned configuration for this device and workload shape (tuned
+    and cached when missing or when retune is set)."""
+    n = int(pos.shape[0] if pos.dim() == 2 and pos.shape[1] in (4, 8) else pos.shape[1])
+    k = system_key(n, rho, rc + skin, kind, precision)
     cache = load_cache(cache_path)
     if k in cache and not retune:
         return cache[k]
-    res = tune(ctx, pos, box, rc, skin, kind, precision, log=log)
+    res = tune(ctx, pos, box, rc, skin, kind, precision, objective=objective, space=space,
+               log=log)
     cache[k] = res["best"]
     save_cache(cache, cache_path)
     return res["best"]

@@ -1,10 +1,12 @@
-"""Measured workloads beyond the default benchmark: the 4M-atom NVE run and
-the 512-system batched NVE run.  Each returns one result dictionary in the
-benchmark's JSON format (pair interactions per second of whole MD steps,
-with per-phase kernel times from HIP events on the library's stream).
+"""Measured workloads beyond the 131k-atom force benchmark: the 4M-atom NVE
+run, the 512-system batched NVE run and the 10,000-step mixed-precision
+accuracy run.  Each returns a result dictionary (pair interactions per
+second of whole MD steps, with per-phase kernel times from HIP events on the
+library's stream).
 
-An MD step here is: drift, the in-place list rebuild every 10th step, forces,
-kick, and the per-step log; 100 steps captured as HIP-graph cycles of 10.
+An MD step here is: drift, the in-place list rebuild (every 10th step, or
+when an atom has moved more than skin/2), forces, kick, and the per-step
+log; runs are captured as HIP-graph cycles of 10 steps.
 """
 from __future__ import annotations
 
@@ -34,45 +36,88 @@ def _sync(ctx) -> bool:
     return False
 
 
-def _nve_run(ctx, pos, vel, force, box, eps, sigma, rc, nl, dt, steps, precision, batch,
-             warmup=10, every=10):
-    """Time `steps` graph-cycle NVE steps after `warmup` untimed ones (rounded
-    up to whole rebuild cycles: the first cycle captures the HIP graph, host
-    work that would otherwise sit inside the timed region).  Returns the
-    milliseconds of the timed steps and the whole log (warmup + steps + 1
-    rows)."""
+def _state(pos0: np.ndarray, vel0: np.ndarray, layout: int, dev):
+    """Device arrays (pos, vel, force) for a run in `layout`: AoS4 records,
+    or LJ_AOS8 position-velocity records (vel is then None; forces AoS4)."""
     import torch
-    warm = -(-max(int(warmup), 0) // every) * every
-    nve = lj.NVE(ctx, pos, vel, force, box, eps, sigma, rc, nl, dt, every, precision,
-                 log_rows=warm + steps + 1, batch=batch)
-    nve.init()
-    if warm:
-        nve.run(warm, use_graph=True)
-    stale = _sync(ctx)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(ctx.stream)
-    nve.run(steps, use_graph=True)
-    ev1.record(ctx.stream)
-    stale = _sync(ctx) or stale
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    log = nve.log.cpu().numpy().copy()
-    nve.free()
-    return ms, log, stale
+    if layout == lj.LJ_AOS8:
+        rec = np.zeros((pos0.shape[0], 8))
+        rec[:, :3] = pos0
+        rec[:, 4:7] = vel0
+        pos = torch.from_numpy(rec).to(dev)
+        return pos, None, torch.zeros((pos0.shape[0], 4), dtype=torch.float64, device=dev)
+    pos = torch.from_numpy(synth.aos4(pos0)).to(dev)
+    vel = torch.from_numpy(synth.aos4(vel0)).to(dev)
+    return pos, vel, torch.zeros_like(pos)
 
 
-def _phase_profile(ctx, pos, vel, force, box, eps, sigma, rc, nl, dt, precision, batch, steps=20):
-    """Per-phase device time per step (us) from the library's profiler on eager steps."""
-    nve = lj.NVE(ctx, pos, vel, force, box, eps, sigma, rc, nl, dt, 10, precision,
-                 log_rows=0, batch=batch)
-    nve.init()
-    ctx.profile_begin()
-    nve.run(steps, use_graph=False)
-    prof = ctx.profile_end()
-    nve.free()
-    return {k: round(v[0] * 1e3 / steps, 3) for k, v in prof.items()}
+def nve_measure(ctx, pos0, vel0, box, rc, steps: int, precision: int, every: int = 10,
+                layout: int = lj.LJ_AOS4, batch_n=None, lanes: int = 0, warmup: int = 10,
+                profile_steps: int = 20) -> dict:
+    """One NVE measurement (eps = sigma = 1, dt = 0.005, full list): `steps`
+    HIP-graph steps timed with HIP events on the context's stream after
+    `warmup` untimed ones (rounded up to whole cycles of 10: the first cycle
+    captures the graph), then the per-phase device time of `profile_steps`
+    eager steps from the library's profiler.  batch_n: the atom counts of a
+    batch (box and rc per system), else one system."""
+    import torch
+    dev = torch.device("cuda:0")
+    batch = batch_n is not None
+    ones = np.ones(len(batch_n)) if batch else 1.0
+    res = {}
+    with torch.cuda.stream(ctx.stream):
+        pos, vel, force = _state(pos0, vel0, layout, dev)
+        torch.cuda.synchronize()
+        if batch:
+            nl = lj.lj_build_neighbors_batch(ctx, pos, batch_n, box, rc, 0.3,
+                                             kind=lj.LJ_LIST_FULL, lanes=lanes)
+        else:
+            nl = lj.lj_build_neighbors(ctx, pos, box, rc, 0.3, kind=lj.LJ_LIST_FULL, lanes=lanes)
+        entries = nl.info().entries
+        warm = -(-max(int(warmup), 0) // 10) * 10
+        nve = lj.NVE(ctx, pos, vel, force, box, ones, ones, rc, nl, 0.005, every, precision,
+                     log_rows=warm + steps + 1, batch=batch)
+        nve.init()
+        if warm:
+            nve.run(warm, use_graph=True)
+        stale = _sync(ctx)
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record(ctx.stream)
+        nve.run(steps, use_graph=True)
+        ev1.record(ctx.stream)
+        stale = _sync(ctx) or stale
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        log = nve.log.cpu().numpy().copy()
+        nve.free()
+        # per-phase device times of eager steps (a fresh integrator, same state)
+        nve = lj.NVE(ctx, pos, vel, force, box, ones, ones, rc, nl, 0.005, every, precision,
+                     log_rows=0, batch=batch)
+        nve.init()
+        ctx.profile_begin()
+        nve.run(profile_steps, use_graph=False)
+        prof = ctx.profile_end()
+        stale = _sync(ctx) or stale
+        nve.free()
+        nl.free()
+    if log.ndim == 2:
+        log = log[:, None, :]
+    timed = log[warm + 1:]
+    pairs = float(timed[:, :, 4].sum(axis=1).mean())
+    between = timed[:, :, 5] == 0.0
+    res = {"ms_per_step": round(ms / steps, 4),
+           "pairs_per_s": round(pairs / (ms / steps * 1e-3), 1),
+           "phase_us_per_step": {k: round(v[0] * 1e3 / profile_steps, 3)
+                                 for k, v in prof.items()},
+           "energy_drift_per_1000_steps": _drift(log, 0.005),
+           "list_entries": int(entries),
+           "rebuilds": int(timed[:, 0, 5].sum()),
+           "max_displacement_between_builds": float(timed[:, :, 3].max()),
+           "list_stale": bool(stale)}
+    res["force_pairs_per_s"] = round(pairs / (res["phase_us_per_step"]["force"] * 1e-6), 1)
+    return res
 
 
 def _drift(log, dt, e_index=None):
@@ -86,60 +131,54 @@ def _drift(log, dt, e_index=None):
     return float(np.polyfit(x, y, 1)[0] * 1000.0)
 
 
-def bench_lj4m(steps: int = 100, warmup: int = 0, cpu: bool = False):
+def bench_lj4m(steps: int = 100, warmup: int = 10, variants: bool = True) -> dict:
+    """The 4,000,000-atom fluid (100^3 FCC cells, rho = 0.85, Maxwell T = 1.0,
+    rc = 2.5, skin 0.3, dt = 0.005), 100 velocity-Verlet steps in HIP-graph
+    cycles, full list: FP64 and mixed with the configured rebuild every 10
+    steps (whether the list went stale is reported); with `variants` also
+    FP64 with the displacement rule (rebuild_every = 0: the list stays
+    exact), with the kicks in separate kernels instead of folded into the
+    force pass, and with (x, y, z, pad, vx, vy, vz, pad) records."""
     import torch
-    dev = torch.device("cuda:0")
     s = synth.lj4m()
     ctx = lj.Context(0, stream=torch.cuda.Stream())
     out = {}
-    for prec_name, prec in (("fp64", lj.LJ_FP64), ("mixed", lj.LJ_MIXED)):
-        with torch.cuda.stream(ctx.stream):
-            pos = torch.from_numpy(synth.aos4(s.pos)).to(dev)
-            vel = torch.from_numpy(synth.aos4(s.vel)).to(dev)
-            force = torch.zeros_like(pos)
-            torch.cuda.synchronize()
-            nl = lj.lj_build_neighbors(ctx, pos, s.box, s.rc, s.skin, kind=lj.LJ_LIST_FULL)
-            ms, log, stale = _nve_run(ctx, pos, vel, force, s.box, 1.0, 1.0, s.rc, nl, 0.005, steps,
-                               prec, False, warmup)
-            prof = _phase_profile(ctx, pos, vel, force, s.box, 1.0, 1.0, s.rc, nl, 0.005, prec,
-                                  False)
-            entries = nl.info().entries
-            nl.free()
-        _note(f"lj4m: {prec_name} done")
-        pairs = float(log[1:, 4].mean())
-        out[prec_name] = {"ms_per_step": round(ms / steps, 4),
-                          "pairs_per_s": round(pairs / (ms / steps * 1e-3), 1),
-                          "force_pairs_per_s": round(pairs / (prof["force"] * 1e-6), 1),
-                          "phase_us_per_step": prof,
-                          "energy_drift_per_1000_steps": _drift(log, 0.005),
-                          "list_entries": entries}
+    runs = [("fp64", lj.LJ_FP64, 10, lj.LJ_AOS4, 0), ("mixed", lj.LJ_MIXED, 10, lj.LJ_AOS4, 0)]
+    if variants:
+        runs += [("fp64_displacement_rule", lj.LJ_FP64, 0, lj.LJ_AOS4, 0),
+                 ("fp64_separate_kicks", lj.LJ_FP64, 10, lj.LJ_AOS4, 2),
+                 ("fp64_aos8_records", lj.LJ_FP64, 10, lj.LJ_AOS8, 0)]
+    for name, prec, every, layout, kick in runs:
+        ctx.tune_set(lj.LJ_TUNE_KICK, kick)
+        out[name] = nve_measure(ctx, s.pos, s.vel, s.box, s.rc, steps, prec, every, layout,
+                                warmup=warmup)
+        ctx.tune_set(lj.LJ_TUNE_KICK, 0)
+        _note(f"lj4m: {name} done")
     f64 = out["fp64"]
     force_bytes = s.n * (32 + 32 + 8) + 4 * f64["list_entries"]
-    gbs = force_bytes / (f64["phase_us_per_step"]["force"] * 1e-6) / 1e9
-    return {
-        "metric": "pair interactions/s (FP64 vs FP32/FP64-mixed) at rho=1, rc=3; HBM GB/s",
-        "value": f64["pairs_per_s"], "unit": "pair interactions/s", "n_gpus": 1,
-        "steps": steps, "warmup": warmup, "ms_per_step": f64["ms_per_step"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "FP64 LJ fluid, 4,000,000 atoms (100^3 FCC x4), rho=0.85, "
-                               "Maxwell T=1.0, rc=2.5, skin=0.3, velocity-Verlet steps at "
-                               "dt=0.005, list rebuilt every 10 steps, HIP-graph cycles; "
-                               f"{steps} steps timed after {-(-max(warmup, 0) // 10) * 10} "
-                               "untimed (graph capture)",
-                   "atoms": s.n, "list": "full", "layout": "aos4"},
-        "roofline": {"kernel": "k_force (FP64, full list)", "bound": "hbm",
-                     "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                     "bytes_per_launch": force_bytes,
-                     "us_per_launch": f64["phase_us_per_step"]["force"]},
-        "fp64": f64, "mixed": out["mixed"],
-        "mixed_speedup_force": round(f64["phase_us_per_step"]["force"] /
-                                     out["mixed"]["phase_us_per_step"]["force"], 3),
-    }
+    fus = f64["phase_us_per_step"]["force"]
+    out["force_roofline"] = {"kernel": "k_force (FP64, full list, kicks folded in)",
+                             "bound": "hbm", "bytes_per_launch": force_bytes,
+                             "us_per_launch": fus,
+                             "achieved": round(force_bytes / (fus * 1e-6) / 1e9, 1),
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(force_bytes / (fus * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}
+    out["mixed_speedup_force"] = round(fus / out["mixed"]["phase_us_per_step"]["force"], 3)
+    out["mixed_speedup_step"] = round(f64["ms_per_step"] / out["mixed"]["ms_per_step"], 3)
+    out["workload"] = ("FP64 and mixed LJ fluid, 4,000,000 atoms (100^3 FCC x4), rho=0.85, "
+                       "Maxwell T=1.0, rc=2.5, skin=0.3, dt=0.005, velocity-Verlet steps in "
+                       f"HIP-graph cycles of 10, {steps} steps timed after "
+                       f"{-(-max(warmup, 0) // 10) * 10} untimed")
+    ctx.close()
+    return out
 
 
-def bench_batch512(steps: int = 100, warmup: int = 0, cpu: bool = False):
+def bench_batch512(steps: int = 100, warmup: int = 10, tune: bool = False) -> dict:
+    """512 independent systems (about 4.3M atoms): 100 NVE steps in HIP-graph
+    cycles with one launch per phase for every system, FP64 and mixed, launch
+    shapes from the autotuner's cache (or tuned here with tune=True); the
+    batching gain of one batched force launch over a loop of 512 per-system
+    launches."""
     import torch
     dev = torch.device("cuda:0")
     systems = synth.batch512()
@@ -150,38 +189,31 @@ def bench_batch512(steps: int = 100, warmup: int = 0, cpu: bool = False):
     pos0 = np.concatenate([x.pos for x in systems])
     vel0 = np.concatenate([x.vel for x in systems])
     ctx = lj.Context(0, stream=torch.cuda.Stream())
-    # launch shapes for this batch from the autotuner (timed on the batch itself)
     from . import autotune
-    with torch.cuda.stream(ctx.stream):
-        pos = torch.from_numpy(synth.aos4(pos0)).to(dev)
-        torch.cuda.synchronize()
-        # objective: an NVE step (forces every step, a rebuild every 10)
-        tuned = autotune.tune_batch(ctx, pos, n, box, rc, 0.3, objective="nve_us",
-                                    space={"lanes": (4, 8), "build_lanes": (64, 4),
-                                           "batch": (2, 4), "cell_div": (2,)}, reps=5)
-    best = tuned["best"]
-    autotune.apply(ctx, best)
-    _note(f"batch512: tuned {best}")
-    out = {}
-    for prec_name, prec in (("fp64", lj.LJ_FP64), ("mixed", lj.LJ_MIXED)):
+    key = autotune.batch_key("batch512", lj.LJ_LIST_FULL, lj.LJ_FP64)
+    cache = autotune.load_cache()
+    tuned = None
+    if tune or key not in cache:
         with torch.cuda.stream(ctx.stream):
-            pos = torch.from_numpy(synth.aos4(pos0)).to(dev)
-            vel = torch.from_numpy(synth.aos4(vel0)).to(dev)
-            force = torch.zeros_like(pos)
+            p = torch.from_numpy(synth.aos4(pos0)).to(dev)
             torch.cuda.synchronize()
-            nl = lj.lj_build_neighbors_batch(ctx, pos, n, box, rc, 0.3, kind=lj.LJ_LIST_FULL,
-                                             lanes=best["lanes"])
-            ms, log, stale = _nve_run(ctx, pos, vel, force, None, ones, ones, rc, nl, 0.005, steps,
-                               prec, True, warmup)
-            prof = _phase_profile(ctx, pos, vel, force, None, ones, ones, rc, nl, 0.005, prec,
-                                  True)
-            nl.free()
-        _note(f"batch512: {prec_name} done")
-        pairs = float(log[1:, :, 4].sum(axis=1).mean())
-        out[prec_name] = {"ms_per_step": round(ms / steps, 4),
-                          "pairs_per_s": round(pairs / (ms / steps * 1e-3), 1),
-                          "phase_us_per_step": prof,
-                          "energy_drift_per_1000_steps_total": _drift(log, 0.005)}
+            tuned = autotune.tune_batch(ctx, p, n, box, rc, 0.3, objective="nve_us",
+                                        space={"lanes": (4, 8), "build_lanes": (64, 4),
+                                               "batch": (2, 4), "cell_div": (2,)}, reps=5)
+            del p
+        best = tuned["best"]
+        cache[key] = best
+        if tune:
+            autotune.save_cache(cache)
+    else:
+        best = cache[key]
+    autotune.apply(ctx, best)
+    _note(f"batch512: launch shapes {best}")
+    out = {}
+    for name, prec in (("fp64", lj.LJ_FP64), ("mixed", lj.LJ_MIXED)):
+        out[name] = nve_measure(ctx, pos0, vel0, box, rc, steps, prec, 10, lj.LJ_AOS4,
+                                batch_n=n, lanes=best["lanes"], warmup=warmup)
+        _note(f"batch512: {name} done")
     # batching gain: one batched force launch vs one launch per system
     with torch.cuda.stream(ctx.stream):
         pos = torch.from_numpy(synth.aos4(pos0)).to(dev)
@@ -215,28 +247,22 @@ def bench_batch512(steps: int = 100, warmup: int = 0, cpu: bool = False):
         t_loop = (time.perf_counter() - t0) / 3
         for _, l1, _ in singles:
             l1.free()
-    f64 = out["fp64"]
-    return {
-        "metric": "pair interactions/s (FP64 vs FP32/FP64-mixed) at rho=1, rc=3; HBM GB/s",
-        "value": f64["pairs_per_s"], "unit": "pair interactions/s", "n_gpus": 1,
-        "steps": steps, "warmup": warmup, "ms_per_step": f64["ms_per_step"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": "512 independent LJ systems, N ~ U{256..16384} (total "
-                               f"{int(n.sum())} atoms), rho ~ U[0.7, 1.1], rc ~ U[2.5, 3.0], "
-                               "skin 0.3, jittered FCC, T=1.0; one launch per phase for all "
-                               "systems, NVE as HIP-graph cycles of 10, launch shapes "
-                               f"autotuned on the batch; {steps} steps timed after "
-                               f"{-(-max(warmup, 0) // 10) * 10} "
-                               "untimed (graph capture)",
-                   "systems": len(systems), "atoms": int(n.sum())},
-        "fp64": f64, "mixed": out["mixed"],
-        "autotuned": best,
-        "autotune_results": tuned["results"],
-        "force_batched_ms": round(t_batched * 1e3, 3),
-        "force_per_system_launch_loop_ms": round(t_loop * 1e3, 3),
-        "batching_gain_force": round(t_loop / t_batched, 2),
-    }
+    ctx.close()
+    res = {"workload": "512 independent LJ systems, N ~ U{256..16384} (total "
+                       f"{int(n.sum())} atoms), rho ~ U[0.7, 1.1], rc ~ U[2.5, 3.0], skin 0.3, "
+                       "jittered FCC, T=1.0; one launch per phase for all systems, NVE in "
+                       f"HIP-graph cycles of 10, {steps} steps timed",
+           "systems": len(systems), "atoms": int(n.sum()),
+           "launch_shapes": best, "launch_shapes_from": "tuned now" if tuned else "cache",
+           **out,
+           "mixed_speedup_step": round(out["fp64"]["ms_per_step"] / out["mixed"]["ms_per_step"],
+                                       3),
+           "force_batched_ms": round(t_batched * 1e3, 3),
+           "force_per_system_launch_loop_ms": round(t_loop * 1e3, 3),
+           "batching_gain_force": round(t_loop / t_batched, 2)}
+    if tuned:
+        res["autotune_results"] = tuned["results"]
+    return res
 
 
 def accuracy_lj500k(steps: int = 10000, rebuild_every: int = 10):
