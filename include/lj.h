@@ -210,11 +210,16 @@ LJ_API lj_status lj_list_free(lj_list* list);
 
 /* Read-only device view of a list's layout, for kernels of the caller that
  * consume the list directly.  Rows are the atoms in cell order, grouped in
- * slices of C = 64 / lanes rows; entry k of row c of slice s is
- *   col[(s * (cap / lanes) + k / lanes) * 64 + c * lanes + k % lanes]
- * for k < row_len[s * C + c]; slots past a row's length up to lanes *
- * slice_iters[s] hold the row's own atom.  row_atom[r] is the atom of row r.
- * The pointers stay valid until the list is rebuilt or freed. */
+ * slices of C = 64 / lanes rows.  Entry k of row c of slice s is taken at
+ * step t = k / lanes by lane p = c * lanes + k % lanes of a wavefront, and
+ * sits at
+ *   col[s * (cap / lanes) * 64 + (t / 4) * 256 + p * 4 + t % 4]
+ * for k < row_len[s * C + c] (each lane finds its indices of 4 consecutive
+ * steps in 16 contiguous bytes; cap is a multiple of 4 lanes).  Entries are
+ * cell-sorted ranks: row r is the atom of rank r, row_atom[r] (for a row
+ * r < n), so the atom of entry j is row_atom[j].  Slots past a row's length,
+ * up to slice_iters[s] rounded up to a multiple of 4 steps, hold the row's
+ * own rank.  The pointers stay valid until the list is rebuilt or freed. */
 typedef struct {
     const int32_t* col;
     const int32_t* row_atom;     /* nslices * C */
@@ -372,7 +377,8 @@ LJ_API lj_status lj_nve_free(lj_nve* nve);
                                    rows side by side, at most the list's lanes).
                                    Fixed for a list when it is created. */
 #define LJ_TUNE_FORCE_BATCH 1   /* list entries each lane has in flight in the force
-                                   kernel: 2, 4 or 8; default 4 */
+                                   kernel: 4 or 8 (2 is accepted and runs as 4);
+                                   default 4 */
 #define LJ_TUNE_CELL_DIV 2      /* lists built without caller cells use cells of side
                                    (rc + skin) / k in y and z and half that in x,
                                    k = 1, 2, 3 or 4; default 2 */

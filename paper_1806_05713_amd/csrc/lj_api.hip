@@ -167,6 +167,8 @@ void list_release(lj_list* l) {
     dfree(l->slice_stats);
     dfree(l->acc);
     dfree(l->q32);
+    dfree(l->xy);
+    dfree(l->zz);
     dfree(l->col);
     dfree(l->stats);
     dfree(l->fc);
@@ -347,7 +349,8 @@ lj_status alloc_rows(lj_list* l, hipStream_t stream) {
     if ((st = dmalloc(&l->slice_sys, l->nslices)) || (st = dmalloc(&l->row_atom, rows)) ||
         (st = dmalloc(&l->row_len, rows)) || (st = dmalloc(&l->slice_iters, l->nslices)) ||
         (st = dmalloc(&l->slice_stats, l->nslices)) || (st = dmalloc(&l->stats, l->nsys)) ||
-        (st = dmalloc(&l->dsys, l->nsys)) || (st = dmalloc(&l->fc, l->nsys)))
+        (st = dmalloc(&l->dsys, l->nsys)) || (st = dmalloc(&l->fc, l->nsys)) ||
+        (st = dmalloc(&l->xy, l->n)) || (st = dmalloc(&l->zz, l->n)))
         return st;
     if (l->kind == LJ_LIST_HALF) {
         // the half list's spread force accumulator, zero between force calls
@@ -404,8 +407,9 @@ lj_status build_list(lj_ctx* ctx, const double* pos, int32_t layout, int nsys, c
         if (kind == LJ_LIST_HALF) expect *= 0.5;
         int64_t cap = (int64_t)(1.25 * expect + 32.0);
         if (cap > sy.n) cap = sy.n;
-        cap = ((cap + lanes - 1) / lanes) * lanes;
-        sy.cap = (int32_t)(cap < lanes ? lanes : cap);
+        // whole groups of 4 steps of the lanes of a row
+        cap = ((cap + 4 * lanes - 1) / (4 * lanes)) * (4 * lanes);
+        sy.cap = (int32_t)(cap < 4 * lanes ? 4 * lanes : cap);
     }
     layout_slices(l);
     if ((st = alloc_rows(l, ctx->stream))) {
@@ -431,7 +435,7 @@ lj_status build_list(lj_ctx* ctx, const double* pos, int32_t layout, int nsys, c
             lj_sys& sy = l->hsys[(size_t)s];
             if (hs[(size_t)s].max_row > sy.cap) {
                 int64_t cap = (int64_t)hs[(size_t)s].max_row + hs[(size_t)s].max_row / 16 + lanes;
-                cap = ((cap + lanes - 1) / lanes) * lanes;
+                cap = ((cap + 4 * lanes - 1) / (4 * lanes)) * (4 * lanes);
                 sy.cap = (int32_t)cap;
                 grown = true;
             }
@@ -834,10 +838,12 @@ extern "C" lj_status lj_list_pairs(lj_ctx* ctx, const lj_list* l, int64_t cap, i
         for (int64_t r = 0; r < sy.n; ++r) {
             const int64_t R = sy.slice0 * C + r;
             const int64_t t = r / C, c = r % C;
+            const uint32_t base = (uint32_t)(t * S * LJ_WAVE + c * G * 4);
             for (int e = 0; e < rl[(size_t)R]; ++e) {
-                const int64_t at = sy.col0 + (t * S + e / G) * LJ_WAVE + c * G + (e % G);
+                const int64_t at = sy.col0 + lj_slot(base, (uint32_t)e, G);
                 ij[2 * k] = ra[(size_t)R];
-                ij[2 * k + 1] = col[(size_t)at];
+                // entries are cell-sorted ranks: the atom of rank j is that of row j
+                ij[2 * k + 1] = ra[(size_t)(sy.slice0 * C + (col[(size_t)at] - sy.atom0))];
                 ++k;
             }
         }

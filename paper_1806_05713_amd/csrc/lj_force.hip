@@ -4,8 +4,11 @@
 // One wavefront serves one slice: C = 64 / G rows, G lanes per row.  As in
 // Alg. 3 the i atom's position and force stay in registers for the whole row;
 // each lane walks every G-th entry of its row:
-//   j      = col[slot]                 one coalesced 256-byte load per wavefront
-//   q_j    = pos[j]                    gather (double4: one 32-byte record)
+//   j      = col[slot]                 the cell-sorted rank of the neighbour; a
+//                                      lane loads its indices of 4 steps at once
+//                                      (1 KiB per wavefront)
+//   q_j    = xy[j], z[j]               gathers from the positions copied into
+//                                      rank order (16 + 8 bytes) before the kernel
 //   t      = q_j - q_i, nearest image  t -= L * rint(t / L)
 //   r^2    = (tx*tx + ty*ty) + tz*tz   rounded as in the list build, so the
 //                                      cutoff test selects exactly the pairs
@@ -17,7 +20,7 @@
 //   A     += (sigma/r)^12, B += (sigma/r)^6, count += mask, so that
 //            E = 4 eps (A - B) - count V(rc) and W = sum fs r^2 = 24 eps (2A - B)
 // Mixed precision (LJ_MIXED) gathers 16-byte fixed-point records instead
-// (k_quantize writes them): t is the wrapping integer difference times the
+// (k_gather_copy writes them): t is the wrapping integer difference times the
 // unit L / 2^32, r^2 stays FP64, and the few entries whose r^2 falls within
 // the quantisation band around rc^2 are decided on the FP64 positions after
 // the main loop; the pair terms are FP32.
@@ -167,26 +170,36 @@ __global__ __launch_bounds__(1024) void k_force_reduce(const double4* __restrict
     }
 }
 
-// Mixed precision: each coordinate as a 32-bit fraction of its box length,
-// u = rint(x 2^32 / L) mod 2^32.  A wrapping 32-bit difference u_j - u_i is
-// then the nearest-image displacement in units of L / 2^32 (1.2e-8 at
-// L = 50.8), exact up to the two roundings of u: one 16-byte record per
-// entry instead of 32, and no image arithmetic.  r^2 is formed in FP64 from
-// it; the pair terms are FP32.  One thread per row of the
-// list; the thread of a system's k-th row converts its k-th atom.
-template <int LAYOUT>
-__global__ __launch_bounds__(LJ_BLOCK) void k_quantize(const double* __restrict__ pos, int64_t n,
-                                                       uint32_t qshift, const lj_sys* sys,
-                                                       const int32_t* slice_sys, int C,
-                                                       const lj_fconst* fc,
-                                                       uint4* __restrict__ q32) {
+// The copies the force kernel gathers from, in cell-sorted rank order (the
+// list's entries are ranks, so the rows' neighbours sit close together in
+// memory whatever the caller's atom order): one thread per row of the list;
+// the thread of a system's k-th row reads the position of that row's atom
+// and writes the system's k-th rank.
+//   FP64: (x, y) 16-byte records and z;
+//   mixed: each coordinate as a 32-bit fraction of its box length,
+//     u = rint(x 2^32 / L) mod 2^32.  A wrapping 32-bit difference u_j - u_i
+//     is then the nearest-image displacement in units of L / 2^32 (1.2e-8 at
+//     L = 50.8), exact up to the two roundings of u: one 16-byte record per
+//     entry instead of 24, and no image arithmetic.  r^2 is formed in FP64
+//     from it; the pair terms are FP32.
+template <int LAYOUT, int PREC>
+__global__ __launch_bounds__(LJ_BLOCK) void k_gather_copy(const double* __restrict__ pos,
+                                                          int64_t n, uint32_t qshift,
+                                                          const lj_sys* sys,
+                                                          const int32_t* slice_sys, int C,
+                                                          const int32_t* __restrict__ row_atom,
+                                                          const lj_fconst* fc,
+                                                          double2* __restrict__ xy,
+                                                          double* __restrict__ zz,
+                                                          uint4* __restrict__ q32) {
     const int64_t r = blockIdx.x * (int64_t)LJ_BLOCK + threadIdx.x;
     const int sid = __builtin_amdgcn_readfirstlane(
         slice_sys[(blockIdx.x * (int64_t)LJ_BLOCK) / C]);
     const lj_sys& sy = sys[sid];
     const int64_t t = r - sy.slice0 * C;
     if (t >= sy.n) return;
-    const int64_t i = sy.atom0 + t;
+    const int64_t rank = sy.atom0 + t;
+    const int64_t i = row_atom[r];
     double x, y, z;
     if (LAYOUT == LJ_AOS4) {
         const double4 q = *reinterpret_cast<const double4*>(
@@ -199,8 +212,14 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_quantize(const double* __restrict_
         y = pos[n + i];
         z = pos[2 * n + i];
     }
-    const lj_fconst& f = fc[sid];
-    q32[i] = make_uint4(lj_fix32(x, f.qinv[0]), lj_fix32(y, f.qinv[1]), lj_fix32(z, f.qinv[2]), 0u);
+    if (PREC == LJ_FP64) {
+        xy[rank] = make_double2(x, y);
+        zz[rank] = z;
+    } else {
+        const lj_fconst& f = fc[sid];
+        q32[rank] = make_uint4(lj_fix32(x, f.qinv[0]), lj_fix32(y, f.qinv[1]),
+                               lj_fix32(z, f.qinv[2]), 0u);
+    }
 }
 
 // One wavefront per slice; a block's four slices belong to one system
@@ -217,20 +236,29 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_force(ForceArgs a) {
     block_partials(a, blk, e, w, c, k);
 }
 
-// Half list: the forces from the accumulator, which is cleared for the next
-// evaluation.
+// Half list: the forces from the accumulator (by rank), which is cleared for
+// the next evaluation.  One thread per row of the list: the thread of a
+// system's k-th row takes rank k and stores the force of that row's atom.
 template <int LAYOUT>
 __global__ __launch_bounds__(LJ_BLOCK) void k_acc_out(double* __restrict__ acc, int64_t n16,
-                                                      int64_t n, const int32_t* flags,
+                                                      int64_t n, const lj_sys* sys,
+                                                      const int32_t* slice_sys, int C,
+                                                      const int32_t* __restrict__ row_atom,
+                                                      const int32_t* flags,
                                                       double* __restrict__ f) {
     if (halted(flags)) return;
-    const int64_t i = blockIdx.x * (int64_t)LJ_BLOCK + threadIdx.x;
-    if (i >= n) return;
-    const double x = acc[i], y = acc[16 * n16 + i], z = acc[32 * n16 + i];
-    acc[i] = 0.0;
-    acc[16 * n16 + i] = 0.0;
-    acc[32 * n16 + i] = 0.0;
-    store_f<LAYOUT>(f, n, i, x, y, z);
+    const int64_t r = blockIdx.x * (int64_t)LJ_BLOCK + threadIdx.x;
+    const int sid = __builtin_amdgcn_readfirstlane(
+        slice_sys[(blockIdx.x * (int64_t)LJ_BLOCK) / C]);
+    const lj_sys& sy = sys[sid];
+    const int64_t t = r - sy.slice0 * C;
+    if (t >= sy.n) return;
+    const int64_t k = sy.atom0 + t;
+    const double x = acc[k], y = acc[16 * n16 + k], z = acc[32 * n16 + k];
+    acc[k] = 0.0;
+    acc[16 * n16 + k] = 0.0;
+    acc[32 * n16 + k] = 0.0;
+    store_f<LAYOUT>(f, n, row_atom[r], x, y, z);
 }
 
 template <int G, int U, bool FS>
@@ -257,15 +285,15 @@ lj_status launch_g(lj_ctx* ctx, const ForceArgs& a, bool half, int layout, int p
     return LJ_OK;
 }
 
-// Entries in flight per lane (tuning knob: 2, 4 or 8); the force-shifted
-// truncation is built for 4 only (the knob changes speed, never results).
+// Entries in flight per lane (tuning knob: 4 or 8; 2 runs as 4, since a
+// lane's indices come 4 steps at a time); the force-shifted truncation is
+// built for 4 only (the knob changes speed, never results).
 template <int G>
 lj_status launch_u(lj_ctx* ctx, const ForceArgs& a, bool half, int layout, int prec,
                    int64_t blocks, bool fs) {
     if (fs) return launch_g<G, 4, true>(ctx, a, half, layout, prec, blocks);
-    const int u = ctx->tune[LJ_TUNE_FORCE_BATCH];
-    if (u == 2) return launch_g<G, 2, false>(ctx, a, half, layout, prec, blocks);
-    if (u == 8) return launch_g<G, 8, false>(ctx, a, half, layout, prec, blocks);
+    if (ctx->tune[LJ_TUNE_FORCE_BATCH] == 8)
+        return launch_g<G, 8, false>(ctx, a, half, layout, prec, blocks);
     return launch_g<G, 4, false>(ctx, a, half, layout, prec, blocks);
 }
 
@@ -393,6 +421,8 @@ lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int preci
     a.partials = partials;
     a.acc = l->acc;
     a.q32 = l->q32;
+    a.xy = l->xy;
+    a.zz = l->zz;
     a.n16 = (l->n + 15) / 16;
     a.halt = &ctx->st->flags;
     a.qshift = lj_qshift(layout);
@@ -405,19 +435,26 @@ lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int preci
     const bool fs = o.trunc == LJ_TRUNC_FORCE_SHIFT;
     lj_status st;
     {
-        lj_prof_scope prof(ctx, LJ_PROF_FORCE);
-        if (precision != LJ_FP64 && !o.quantized) {
-            const dim3 qgrid((unsigned)(l->nslices * (LJ_WAVE / l->lanes) / LJ_BLOCK));
-            if (tl == LJ_AOS4)
-                hipLaunchKernelGGL(k_quantize<LJ_AOS4>, qgrid, dim3(LJ_BLOCK), 0, ctx->stream,
-                                   pos, l->n, a.qshift, (const lj_sys*)l->dsys,
-                                   (const int32_t*)l->slice_sys, LJ_WAVE / l->lanes, fc, l->q32);
-            else
-                hipLaunchKernelGGL(k_quantize<LJ_SOA>, qgrid, dim3(LJ_BLOCK), 0, ctx->stream,
-                                   pos, l->n, a.qshift, (const lj_sys*)l->dsys,
-                                   (const int32_t*)l->slice_sys, LJ_WAVE / l->lanes, fc, l->q32);
+        lj_prof_scope prof(ctx, LJ_PROF_OTHER);
+        // the rank-ordered copy of the positions the kernel gathers from
+        {
+            const int C = LJ_WAVE / l->lanes;
+            const dim3 qgrid((unsigned)(l->nslices * C / LJ_BLOCK));
+#define LJ_COPY(L, P)                                                                      \
+    hipLaunchKernelGGL((k_gather_copy<L, P>), qgrid, dim3(LJ_BLOCK), 0, ctx->stream, pos, \
+                       l->n, a.qshift, (const lj_sys*)l->dsys, (const int32_t*)l->slice_sys, C, \
+                       (const int32_t*)l->row_atom, fc, l->xy, l->zz, l->q32)
+            if (tl == LJ_AOS4) {
+                if (precision == LJ_FP64) LJ_COPY(LJ_AOS4, LJ_FP64); else LJ_COPY(LJ_AOS4, LJ_MIXED);
+            } else {
+                if (precision == LJ_FP64) LJ_COPY(LJ_SOA, LJ_FP64); else LJ_COPY(LJ_SOA, LJ_MIXED);
+            }
+#undef LJ_COPY
             LJ_HIP(hipGetLastError());
         }
+    }
+    {
+        lj_prof_scope prof(ctx, LJ_PROF_FORCE);
         switch (l->lanes) {
             case 1: st = launch_u<1>(ctx, a, half, tl, precision, blocks, fs); break;
             case 2: st = launch_u<2>(ctx, a, half, tl, precision, blocks, fs); break;
@@ -433,13 +470,16 @@ lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int preci
     lj_prof_scope prof(ctx, LJ_PROF_OTHER);
     const int32_t* flags = &ctx->st->flags;
     if (half) {
-        const dim3 grid((unsigned)((l->n + LJ_BLOCK - 1) / LJ_BLOCK)), block(LJ_BLOCK);
+        const int C = LJ_WAVE / l->lanes;
+        const dim3 grid((unsigned)(l->nslices * C / LJ_BLOCK)), block(LJ_BLOCK);
         if (tl == LJ_AOS4)
             hipLaunchKernelGGL(k_acc_out<LJ_AOS4>, grid, block, 0, ctx->stream, l->acc, a.n16,
-                               l->n, flags, force);
+                               l->n, (const lj_sys*)l->dsys, (const int32_t*)l->slice_sys, C,
+                               (const int32_t*)l->row_atom, flags, force);
         else
             hipLaunchKernelGGL(k_acc_out<LJ_SOA>, grid, block, 0, ctx->stream, l->acc, a.n16,
-                               l->n, flags, force);
+                               l->n, (const lj_sys*)l->dsys, (const int32_t*)l->slice_sys, C,
+                               (const int32_t*)l->row_atom, flags, force);
         LJ_HIP(hipGetLastError());
     }
     const int split = lj_force_split(l);

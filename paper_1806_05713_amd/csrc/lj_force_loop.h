@@ -9,6 +9,8 @@
 
 namespace ljf {
 
+typedef int v4i __attribute__((ext_vector_type(4)));
+
 struct ForceArgs {
     const double* pos;
     double* force;
@@ -22,9 +24,13 @@ struct ForceArgs {
     const int32_t* slice_iters;
     const int32_t* col;
     double* partials;        // 4 doubles per (logical) block
-    double* acc;             // half list: spread force accumulator (3 x 16 n16 doubles)
+    double* acc;             // half list: spread force accumulator (3 x 16 n16 doubles),
+                             // by rank
     int64_t n16;
-    uint4* q32;              // mixed: fixed-point positions (x, y, z as fractions of the box)
+    uint4* q32;              // mixed: fixed-point positions (x, y, z as fractions of the
+                             // box) in cell-sorted rank order
+    const double2* xy;       // FP64: the positions in cell-sorted rank order, split into
+    const double* zz;        // (x, y) records and z: one 16-byte and one 8-byte gather
     const int32_t* halt;     // device status flags: the kernel does nothing once an
                              // error flag is raised (NULL: never)
     uint32_t qshift;         // AoS record stride as a shift: 5 (32-byte records) or 6
@@ -143,10 +149,11 @@ __device__ __forceinline__ double kick_row(const ForceArgs& a, int64_t i, double
     return ke;
 }
 
-// Loads are issued U entries at a time, and the indices of the next U
-// entries are requested before the current ones are computed, so each
-// wavefront keeps up to 3U gathers and U index loads in flight (the
-// load/compute overlap that software pipelining gives a CPU core).
+// Loads are issued U entries (U / 4 groups of 4 steps) at a time, and the
+// indices of the next U entries are requested before the current ones are
+// computed, so each wavefront keeps up to 2U gathers and U / 4 index loads in
+// flight (the load/compute overlap that software pipelining gives a CPU
+// core).
 // The forces of one slice of system sid, computed by the calling wavefront
 // (C = 64 / G rows, G lanes per row); returns the lane's shares of the
 // energy, the virial, the pair count and (with a kick) the kinetic energy,
@@ -164,32 +171,50 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
     const int iters = __builtin_amdgcn_readfirstlane(a.slice_iters[slice]);
     const int c = lane / G, g = lane % G;
     const int64_t r = (int64_t)slice * C + c;
-    const int i = a.row_atom[r];
+    const int i = a.row_atom[r];        // the row's atom (forces, velocities)
     const int lim = a.row_len[r] - g;   // entry it*G + g is inside the row iff it*G < lim
-    const bool row_ok = (r - sy.slice0 * C) < sy.n;
+    const int64_t lr = r - sy.slice0 * C;
+    const bool row_ok = lr < sy.n;
+    // its cell-sorted rank (entries, gathered copies and the half list's
+    // accumulator are indexed by rank)
+    const int ri = (int)(sy.atom0 + (row_ok ? lr : 0));
     const double bx = sy.box[0], by = sy.box[1], bz = sy.box[2];
     const double ibx = sy.inv_box[0], iby = sy.inv_box[1], ibz = sy.inv_box[2];
     const double rc2 = fc.rc2;
     double qx, qy, qz;
-    gather_q<LAYOUT>(a.pos, a.n, a.qshift, i, qx, qy, qz);
+    if constexpr (PREC == LJ_FP64) {
+        const double2 q = a.xy[ri];
+        qx = q.x;
+        qy = q.y;
+        qz = a.zz[ri];
+    } else {
+        gather_q<LAYOUT>(a.pos, a.n, a.qshift, i, qx, qy, qz);
+    }
 
     const char* colbase = reinterpret_cast<const char*>(
         a.col + sy.col0 + (int64_t)(slice - sy.slice0) * (sy.cap / G) * LJ_WAVE);
-    const uint32_t lane_off = (uint32_t)lane * 4u;
+    const uint32_t lane_off = (uint32_t)lane * 16u;
     double fx = 0.0, fy = 0.0, fz = 0.0, sA = 0.0, sB = 0.0, sR = 0.0;
     int cnt = 0;
 
-    // slot of step `it`, clamped into the slice so that every index load is
-    // unconditional (no branch for the compiler to wait behind)
-    const int last = iters > 0 ? iters - 1 : 0;
-    auto idx_at = [&](int it) -> int {
-        const int k = it < last ? it : last;
+    // The lane's indices of steps 4 q .. 4 q + 3: one 16-byte load from the
+    // slice's group q, clamped into the slice so that every index load is
+    // unconditional (no branch for the compiler to wait behind).
+    constexpr int NQ = U / 4;                 // groups of 4 steps per batch
+    const int lastq = iters > 0 ? (iters - 1) >> 2 : 0;
+    auto group_at = [&](int q) -> v4i {
+        const int k = q < lastq ? q : lastq;
         return __builtin_nontemporal_load(
-            reinterpret_cast<const int*>(colbase + (uint32_t)(k * LJ_WAVE * 4) + lane_off));
+            reinterpret_cast<const v4i*>(colbase + (uint32_t)(k * LJ_WAVE * 16) + lane_off));
     };
-    int jn[U];
+    // the lane's index of step `it` alone (the rare exact pass of the mixed kernel)
+    auto idx_at = [&](int it) -> int {
+        return *reinterpret_cast<const int*>(colbase + (uint32_t)((it >> 2) * LJ_WAVE * 16) +
+                                             lane_off + (uint32_t)(it & 3) * 4u);
+    };
+    v4i jq[NQ];
 #pragma unroll
-    for (int u = 0; u < U; ++u) jn[u] = idx_at(u);
+    for (int q = 0; q < NQ; ++q) jq[q] = group_at(q);
     // the force constants as values, read once
     const double sig2 = fc.sig2, c24 = fc.c24, c48 = fc.c48;
     const float sig2f = fc.sig2f, c24f = fc.c24f, c48f = fc.c48f;
@@ -200,7 +225,7 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
     // mixed: the row atom's fixed-point record; whether the lane met an entry
     // whose r^2 lies in the quantisation band of rc^2 (decided after the loop)
     uint4 qi4 = make_uint4(0u, 0u, 0u, 0u);
-    if constexpr (PREC != LJ_FP64) qi4 = a.q32[i];
+    if constexpr (PREC != LJ_FP64) qi4 = a.q32[ri];
     bool had_amb = false;
     // pair terms of an interacting entry from its r^2 (mixed: FP32 terms);
     // rr: the pair's distance r for the force-shifted energy (0 if masked)
@@ -240,10 +265,22 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
     for (int it0 = 0; it0 < iters; it0 += U) {
         double px[U], py[U], pz[U];
         uint4 qv[U];
-        if constexpr (PREC == LJ_FP64) {
+        int jn[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                gather_q<LAYOUT>(a.pos, a.n, a.qshift, jn[u], px[u], py[u], pz[u]);
+        for (int u = 0; u < U; ++u) jn[u] = jq[u >> 2][u & 3];
+        if constexpr (PREC == LJ_FP64) {
+            // the (x, y) record and z of each entry: 24 bytes over 16- and
+            // 8-byte records (the 8 entries a row takes per step span about
+            // half the cache lines of 32-byte records)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const double2 q = *reinterpret_cast<const double2*>(
+                    reinterpret_cast<const char*>(a.xy) + (uint32_t)jn[u] * 16u);
+                px[u] = q.x;
+                py[u] = q.y;
+                pz[u] = *reinterpret_cast<const double*>(
+                    reinterpret_cast<const char*>(a.zz) + (uint32_t)jn[u] * 8u);
+            }
         } else {
 #pragma unroll
             for (int u = 0; u < U; ++u) qv[u] = a.q32[jn[u]];
@@ -252,7 +289,7 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
 #pragma unroll
         for (int u = 0; u < U; ++u) jc[u] = jn[u];
 #pragma unroll
-        for (int u = 0; u < U; ++u) jn[u] = idx_at(it0 + U + u);
+        for (int q = 0; q < NQ; ++q) jq[q] = group_at((it0 + U) / 4 + q);
         // keep the next indices' loads issued here, ahead of the arithmetic
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -299,8 +336,10 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
                 fixed_disp(a.q32[j], tx, ty, tz);
                 const double r2 = r2_rounded(tx, ty, tz);
                 if (r2 < rc2lo || !(r2 < rc2hi)) continue;
+                // the atom of rank j: the row of that rank
+                const int aj = a.row_atom[sy.slice0 * C + (j - sy.atom0)];
                 double ex, ey, ez;
-                gather_q<LAYOUT>(a.pos, a.n, a.qshift, j, ex, ey, ez);
+                gather_q<LAYOUT>(a.pos, a.n, a.qshift, aj, ex, ey, ez);
                 ex = ex - qx;
                 ey = ey - qy;
                 ez = ez - qz;
@@ -331,7 +370,7 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
     double ke = 0.0;
     if (g == 0 && row_ok) {
         if (HALF) {
-            acc_add(a.acc, a.n16, i, fx, fy, fz);
+            acc_add(a.acc, a.n16, ri, fx, fy, fz);
         } else if (a.kick == LJ_KICK_NONE) {
             store_f<LAYOUT>(a.force, a.n, i, fx, fy, fz);
         } else {

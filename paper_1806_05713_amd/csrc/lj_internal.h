@@ -19,12 +19,15 @@
 //              multiple of 4G (whole 256-row blocks), so that every
 //              wavefront, 4-slice force block and 256-row block belongs to one
 //              system; row r of the system is rank atom0 + r - slice0 * C.
-//              Entry k of row c of slice t (local index t - slice0) is at
-//                col[col0 + (t_local * (cap / G) + k / G) * 64 + c * G + k % G]
-//              so one 64-lane load fetches 256 contiguous bytes.  row_atom,
-//              row_len per row; slice_iters[t] = the slice's longest row in
-//              G-wide steps; slots past a row's length (up to its slice's
-//              length) hold the row's own atom so every gather stays in bounds.
+//              Entry k of row c of slice t (local index t - slice0) is taken
+//              at step s = k / G by lane p = c * G + k % G and sits at
+//                col[col0 + t_local * (cap / G) * 64 + (s / 4) * 256 + p * 4 + s % 4]
+//              so each lane loads its indices of 4 consecutive steps with one
+//              16-byte load (1 KiB per wavefront).  cap is a multiple of 4 G.
+//              row_atom, row_len per row; slice_iters[t] = the slice's longest
+//              row in G-wide steps; slots past a row's length (up to its
+//              slice's length rounded up to 4 steps) hold the row's own atom
+//              so every gather stays in bounds.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -177,7 +180,10 @@ struct lj_list {
     bool fc_valid;
     lj_cells* cells;               // owned cell structure for in-place rebuilds (lazy)
     double* acc;                   // half list: spread force accumulator, zero between calls
-    uint4* q32;                    // mixed precision: fixed-point positions (n records, lazy)
+    uint4* q32;                    // mixed precision: fixed-point positions (n records by
+                                   // cell-sorted rank, lazy)
+    double2* xy;                   // FP64 forces gather from this copy of the positions by
+    double* zz;                    // cell-sorted rank: (x, y) 16-byte records and z
 };
 
 // ---------------------------------------------------------------- errors
@@ -240,8 +246,6 @@ lj_status lj_scratch_partials(int device, double** ptr);
 // LJ_MIXED needs the list's fixed-point position buffer (lj_list_ensure_q32,
 // called before any launch that a graph may capture).
 struct lj_force_opts {
-    bool quantized = false;       // mixed: the list's fixed-point buffer already holds pos
-                                  // (written by the integrator's drift)
     double* partials = nullptr;   // block partials (double4 records); NULL: the context's
     int64_t partials_cap = 0;     // their capacity in records
     int trunc = LJ_TRUNC_SHIFT;   // must match the constants in fc
@@ -281,6 +285,12 @@ lj_status lj_launch_zero(hipStream_t s, void* p, int64_t bytes);
 lj_fconst lj_make_fconst(double eps, double sigma, double rc, const double box[3], int trunc);
 
 // ------------------------------------------------------- device helpers
+// Offset of entry k of a row from its slot base (the slice's first slot plus
+// 4 c G for row c of the slice; layout above).
+__host__ __device__ __forceinline__ uint32_t lj_slot(uint32_t base, uint32_t k, int G) {
+    const uint32_t s = k / (uint32_t)G;
+    return base + (s >> 2) * 256u + (k % (uint32_t)G) * 4u + (s & 3u);
+}
 // Logical block index that gives each XCD a contiguous range of blocks
 // (the dispatcher deals consecutive workgroups round-robin to the 8 XCDs,
 // each of which has its own L2).  A bijection on [0, nb).

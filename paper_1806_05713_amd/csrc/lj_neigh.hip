@@ -281,12 +281,13 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
     int32_t* __restrict__ wcol =
         a.col + sy.col0 + (slice_first - sy.slice0) * (int64_t)S * LJ_WAVE;
     const uint32_t lane_slot =
-        (uint32_t)((slice - slice_first) * (int64_t)S * LJ_WAVE) + (uint32_t)(c * G);
+        (uint32_t)((slice - slice_first) * (int64_t)S * LJ_WAVE) + (uint32_t)(c * G * 4);
     const int32_t* __restrict__ cell_start = a.cell_start + sy.cell0;
     const char* __restrict__ spos_b = reinterpret_cast<const char*>(a.spos);
 
     const double4 qi = a.spos[rank];
-    const int32_t self = (int32_t)__double_as_longlong(qi.w);
+    const int32_t self_atom = (int32_t)__double_as_longlong(qi.w);
+    const int32_t self = r32;   // entries are cell-sorted ranks; the row's own rank pads it
     const Stencil stn = make_stencil<ANYFULL>(sy);
     const RowGeo geo = row_geo(stn, qi, row_ok);
     const bool fullx = stn.fullx, fully = stn.fully, fullz = stn.fullz;
@@ -313,9 +314,9 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
         const double r2 = r2_rounded(tx, ty, tz);
         bool own = true;
         if (HALF) own = ((s > r32) != (((s + r32) & 1) != 0));
-        jv = (int32_t)__double_as_longlong(qj.w);
+        jv = s;
         // bitwise: no short-circuit branch around the loads; the candidate is
-        // the row's own atom iff its index is
+        // the row's own atom iff its rank is
         return (jv != self) & own & (r2 < rs2);
     };
     auto test = [&](int s, double shx, double shy, double shz, bool shifted_x, int32_t& jv) {
@@ -324,9 +325,7 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
     };
     // entry k of the row: one store through the wavefront's base with a
     // 32-bit offset
-    auto put = [&](uint32_t k, int32_t jv) {
-        wcol[lane_slot + (k / (uint32_t)G) * (uint32_t)LJ_WAVE + (k % (uint32_t)G)] = jv;
-    };
+    auto put = [&](uint32_t k, int32_t jv) { wcol[lj_slot(lane_slot, k, G)] = jv; };
     auto scan = [&](int s0, int m, double shx, double shy, double shz, bool shifted_x) {
         if (GB == 1) {
             // one lane per row: each lane appends to its own row, no ballot;
@@ -405,10 +404,12 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
         ntest += __shfl_xor(ntest, d, LJ_WAVE);
     }
     const int iters = (mx + G - 1) / G;
-    // pad the row up to the slice length with the row's own atom
-    for (int k = len + g; k < iters * G; k += GB) put((uint32_t)k, self);
+    // pad the row with the row's own atom up to the slice length rounded to
+    // whole groups of 4 steps (the force kernel loads a lane's indices 4 steps
+    // at a time)
+    for (int k = len + g; k < ((iters + 3) & ~3) * G; k += GB) put((uint32_t)k, self);
     if (g == 0) {
-        a.row_atom[R] = row_ok ? self : 0;
+        a.row_atom[R] = row_ok ? self_atom : 0;
         a.row_len[R] = row_ok ? len : 0;
         if (cnt > cap) atomicOr(&a.st->flags, LJ_DEV_ROW_OVERFLOW);   // rare: no contention
     }
@@ -546,12 +547,10 @@ __global__ __launch_bounds__(LJ_BLOCK, 7) void k_neigh_rows(NeighArgs a) {
     const float r2lo = sy.r2lo, r2hi = sy.r2hi;
     const Stencil stn = make_stencil<ANYFULL>(sy);
 
-    // entry k of the row at slot offset `slot`
-    auto put = [&](uint32_t slot, uint32_t k, int32_t v) {
-        wcol[slot + (k / (uint32_t)G) * (uint32_t)LJ_WAVE + (k % (uint32_t)G)] = v;
-    };
+    // entry k of the row whose slots start at `slot`
+    auto put = [&](uint32_t slot, uint32_t k, int32_t v) { wcol[lj_slot(slot, k, G)] = v; };
     auto row_slot = [&](int rr) {
-        return (uint32_t)((rr / C) * S * LJ_WAVE + (rr % C) * G);
+        return (uint32_t)((rr / C) * S * LJ_WAVE + (rr % C) * G * 4);
     };
 
     int keep_len = 0, keep_self = 0, keep_atom = 0;   // lane r: row r of the wavefront
@@ -613,7 +612,8 @@ __global__ __launch_bounds__(LJ_BLOCK, 7) void k_neigh_rows(NeighArgs a) {
             const bool okh = lrh < nsys;
             const int rh = okh ? (int)lrh : 0;
             const double4 qi = rq[rr];
-            const int32_t self = (int32_t)__double_as_longlong(qi.w);
+            const int32_t self_atom = (int32_t)__double_as_longlong(qi.w);
+            const int32_t self = atom0 + rh;   // entries are ranks; the row's own pads it
             const uint32_t slot = row_slot(rr);
             int cnt = 0;
 
@@ -662,10 +662,10 @@ __global__ __launch_bounds__(LJ_BLOCK, 7) void k_neigh_rows(NeighArgs a) {
                 }
                 const double r2 = r2_rounded(tx, ty, tz);
                 uint64_t pass = __builtin_amdgcn_ballot_w64(r2 < rs2) & valid &
-                                __builtin_amdgcn_ballot_w64(q.j != self);
+                                __builtin_amdgcn_ballot_w64(srel != rh);
                 if (HALF) pass &= __builtin_amdgcn_ballot_w64((srel > rh) !=
                                                               (((srel + rh) & 1) != 0));
-                append(pass, q.j);
+                append(pass, atom0 + srel);
             };
             // table entry of the lane's stream position in tile t
             auto entry = [&](int t) {
@@ -739,11 +739,10 @@ __global__ __launch_bounds__(LJ_BLOCK, 7) void k_neigh_rows(NeighArgs a) {
                         }
                         exact = __builtin_amdgcn_ballot_w64(ex) & amb;
                     }
-                    const int32_t j = (int32_t)v[3];
-                    uint64_t pass = (in | exact) & __builtin_amdgcn_ballot_w64(j != self);
+                    uint64_t pass = (in | exact) & __builtin_amdgcn_ballot_w64(srel != rh);
                     if (HALF) pass &= __builtin_amdgcn_ballot_w64((srel > rh) !=
                                                                   (((srel + rh) & 1) != 0));
-                    append(pass, j);
+                    append(pass, atom0 + srel);
                 }
             };
             if (T <= RT_NT * LJ_WAVE && E <= RT_MAXE) {
@@ -778,38 +777,21 @@ __global__ __launch_bounds__(LJ_BLOCK, 7) void k_neigh_rows(NeighArgs a) {
             }
 
             const int len = cnt < cap ? cnt : cap;
-            // write out the staged entries, SW per lane (runs of G entries are
-            // contiguous in the layout), the last group completed with the
-            // row's own atom
+            // write out the staged entries, one per lane and pass (64
+            // consecutive entries of a row fill whole 128-byte runs of the
+            // layout), the last group of G completed with the row's own atom
             {
-                constexpr int SW = G < 4 ? G : 4;
                 wave_lds_sync();
-                const int fl = len <= RT_RB ? (len + SW - 1) / SW * SW : RT_RB;
+                const int fl = len <= RT_RB ? (len + G - 1) / G * G : RT_RB;
                 const int* rowb = reinterpret_cast<const int*>(tb.row);
-                for (int k0 = lane * SW; k0 < fl; k0 += LJ_WAVE * SW) {
-                    int32_t* dst = wcol + slot + (uint32_t)(k0 / G) * LJ_WAVE + (uint32_t)(k0 % G);
-                    if constexpr (SW == 4) {
-                        int4 v = tb.row[k0 / 4];
-                        v.x = k0 < len ? v.x : self;
-                        v.y = k0 + 1 < len ? v.y : self;
-                        v.z = k0 + 2 < len ? v.z : self;
-                        v.w = k0 + 3 < len ? v.w : self;
-                        *reinterpret_cast<int4*>(dst) = v;
-                    } else if constexpr (SW == 2) {
-                        int2 v = make_int2(rowb[k0], rowb[k0 + 1]);
-                        v.x = k0 < len ? v.x : self;
-                        v.y = k0 + 1 < len ? v.y : self;
-                        *reinterpret_cast<int2*>(dst) = v;
-                    } else {
-                        *dst = k0 < len ? rowb[k0] : self;
-                    }
-                }
+                for (int k = lane; k < fl; k += LJ_WAVE)
+                    put(slot, (uint32_t)k, k < len ? rowb[k] : self);
                 wave_lds_sync();
             }
             if (lane == rr) {
                 keep_len = len;
                 keep_self = self;
-                keep_atom = okh ? self : 0;
+                keep_atom = okh ? self_atom : 0;
             }
             if (cnt > cap && lane == 0) atomicOr(&a.st->flags, LJ_DEV_ROW_OVERFLOW);
             sl_mx = max(sl_mx, len);
@@ -819,14 +801,14 @@ __global__ __launch_bounds__(LJ_BLOCK, 7) void k_neigh_rows(NeighArgs a) {
             if ((rr + 1) % C == 0) {
                 // the slice is complete: pad its rows with their own atom
                 const int iters = (sl_mx + G - 1) / G;
-                constexpr int SW = G < 4 ? G : 4;
+                const int padded = ((iters + 3) & ~3) * G;   // whole groups of 4 steps
                 for (int j = rr + 1 - C; j <= rr; ++j) {
                     const int lj = __builtin_amdgcn_readlane(keep_len, j);
                     const int sj = __builtin_amdgcn_readlane(keep_self, j);
                     const uint32_t sl = row_slot(j);
-                    // written so far: the staged entries rounded up to SW
-                    const int from = lj <= RT_RB ? (lj + SW - 1) / SW * SW : lj;
-                    for (int k = from + lane; k < iters * G; k += LJ_WAVE) put(sl, (uint32_t)k, sj);
+                    // written so far: the staged entries rounded up to G
+                    const int from = lj <= RT_RB ? (lj + G - 1) / G * G : lj;
+                    for (int k = from + lane; k < padded; k += LJ_WAVE) put(sl, (uint32_t)k, sj);
                 }
                 if (lane == 0) {
                     const int64_t slice = slice_first + rr / C;

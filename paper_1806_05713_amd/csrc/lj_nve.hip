@@ -32,13 +32,13 @@
 // The per-atom kernels take one thread per row of the list (256-row blocks,
 // each inside one system), but the thread of a system's k-th row handles the
 // system's k-th atom in memory order: the arrays stream instead of being
-// gathered.  In a mixed-precision run the drift also writes the force
-// kernel's fixed-point positions.  Every product and sum is rounded on its
+// gathered.  Every product and sum is rounded on its
 // own, as in the oracle's integrator.  Bytes per atom (AoS4): kick-drift 208
 // (reads vel, force, pos 32 each and disp 24; writes vel, pos, disp), drift
 // alone 144 (no force, no velocity written), kick 88; a guarded drift writes
 // 64 more; a folded kick adds 64 to the force pass (velocity read and
-// written) and saves its 32-byte force store inside a cycle.
+// written) and saves its 32-byte force store inside a cycle.  The force pass
+// starts with its rank-ordered copy of the positions (56 bytes per atom).
 #include <math.h>
 
 #include <algorithm>
@@ -95,7 +95,6 @@ struct RowArgs {
     int64_t* dstep;
     int32_t* flags;        // the context's device status flags
     int32_t* gate;
-    uint4* q32;            // mixed precision: fixed-point copy written by the drift (or NULL)
     const lj_fconst* fc;   // per system: the fixed-point unit
     double* bpos;
     double* bvel;
@@ -158,11 +157,6 @@ __device__ __forceinline__ double drift_atom(const RowArgs& a, const lj_sys& sy,
         u[d] = un[d];
     }
     store_rec<LAYOUT>(a.pos, a.n, a.rec, i, x);
-    if (a.q32) {
-        const double* inv = a.fc[&sy - a.sys].qinv;   // sy is an element of a.sys
-        a.q32[i] = make_uint4(lj_fix32(x.v[0], inv[0]), lj_fix32(x.v[1], inv[1]),
-                              lj_fix32(x.v[2], inv[2]), 0u);
-    }
     return (un[0] * un[0] + un[1] * un[1]) + un[2] * un[2];
 }
 
@@ -395,7 +389,6 @@ RowArgs row_args(lj_nve* s) {
     a.dstep = s->dstep;
     a.flags = &s->ctx->st->flags;
     a.gate = s->gate;
-    a.q32 = s->precision != LJ_FP64 ? s->list->q32 : nullptr;
     a.fc = s->fc;
     a.bpos = s->bpos;
     a.bvel = s->layout == LJ_AOS8 ? s->bpos + 4 : s->bvel;
@@ -404,11 +397,9 @@ RowArgs row_args(lj_nve* s) {
 }
 
 // The force pass of a step: kick = LJ_KICK_* (folded kicks write the
-// kinetic energy next to the potential energy); after a drift the mixed
-// kernel's fixed-point copy is already current.
-lj_status forces(lj_nve* s, bool after_drift, int kick) {
+// kinetic energy next to the potential energy).
+lj_status forces(lj_nve* s, int kick) {
     lj_force_opts o;
-    o.quantized = after_drift;
     o.partials = s->fpart;
     o.partials_cap = s->fpart_cap;
     o.trunc = s->trunc;
@@ -487,11 +478,11 @@ lj_status enqueue_chain(lj_nve* s, int64_t first, int64_t count) {
             // kick twice unless the next step may rebuild or the chain ends here
             const bool next_guarded = (step + 1) % every == 0;
             const int kick = (k == count || next_guarded) ? LJ_KICK_SYNC : LJ_KICK_LEAP;
-            if ((st = forces(s, true, kick))) return st;
+            if ((st = forces(s, kick))) return st;
             leapt = kick == LJ_KICK_LEAP;
             if ((st = log_row(s, true, 0, rebuild ? 1 : 0, parity))) return st;
         } else {
-            if ((st = forces(s, true, LJ_KICK_NONE))) return st;
+            if ((st = forces(s, LJ_KICK_NONE))) return st;
         }
     }
     if (!s->folded) {
@@ -630,7 +621,7 @@ lj_status lj_nve_start(lj_nve* s) {
     hipLaunchKernelGGL(k_set_state, dim3(1), dim3(1), 0, ctx->stream, s->dstep, s->gate,
                        s->armed);
     LJ_HIP(hipGetLastError());
-    if ((st = forces(s, false, LJ_KICK_NONE))) return st;
+    if ((st = forces(s, LJ_KICK_NONE))) return st;
     // kinetic energy of the initial velocities: a kick of zero length
     const dim3 grid((unsigned)s->rblocks), block(LJ_BLOCK);
     if (tmpl(s) == LJ_AOS4)

@@ -177,7 +177,7 @@ def test_nve_fixed_cadence_reports_stale(lj, ctx, oracle):
     nl.free()
 
 
-def inflow_state(c=12.0):
+def inflow_state(c=14.0):
     """864 atoms of a dilute FCC lattice (rho = 0.074) moving towards the
     box centre with v = -c (x - L/2): the cloud contracts, so a list rebuilt
     after a few steps has rows longer than the capacity sized at the start."""
