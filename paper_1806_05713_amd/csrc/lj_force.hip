@@ -417,6 +417,7 @@ lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int preci
     a.row_atom = l->row_atom;
     a.row_len = l->row_len;
     a.slice_iters = l->slice_iters;
+    a.slice_stats = l->slice_stats;
     a.col = l->col;
     a.partials = partials;
     a.acc = l->acc;

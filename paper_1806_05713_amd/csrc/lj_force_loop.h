@@ -5,6 +5,8 @@
 // Device code only; included by HIP sources.
 #pragma once
 
+#include <type_traits>
+
 #include "lj_internal.h"
 
 namespace ljf {
@@ -22,6 +24,7 @@ struct ForceArgs {
     const int32_t* row_atom;
     const int32_t* row_len;
     const int32_t* slice_iters;
+    const int4* slice_stats;  // per slice, .w: 1 if a row has entries across a periodic face
     const int32_t* col;
     double* partials;        // 4 doubles per (logical) block
     double* acc;             // half list: spread force accumulator (3 x 16 n16 doubles),
@@ -75,14 +78,25 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// 1/x as v_rcp_f64 refined by two Newton steps y <- y (2 - x y) (each step
-// squares the relative error, which v_rcp_f64 already bounds far below 2^-20).
+// 1/x as v_rcp_f64 refined by one Newton step y <- y + y (1 - x y), which
+// squares the relative error: measured on gfx950 over x in [0.25, 35]
+// (the r^2 of the pairs), v_rcp_f64 is within 4.6e-8 of the correctly
+// rounded 1/x and one step within 2.2e-15 (mean 1e-16), far inside the
+// 1e-10 force and 1e-12 energy tolerances of the FP64 path.
 __device__ __forceinline__ double recip(double x) {
-    double y = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, y, 1.0);
-    y = fma(y, e, y);
-    e = fma(-x, y, 1.0);
-    return fma(y, e, y);
+    const double y = __builtin_amdgcn_rcp(x);
+    return fma(y, fma(-x, y, 1.0), y);
+}
+
+// m ? x : x with its high word cleared, which is +0 or a subnormal below
+// 2^-1022 whatever x was (inf and NaN included): its square underflows to an
+// exact zero, so every term built from its square or higher powers is an
+// exact zero (one 32-bit select in place of two).
+__device__ __forceinline__ double keep_or_tiny(bool m, double x) {
+    const long long b = __double_as_longlong(x);
+    const unsigned hi = m ? (unsigned)((unsigned long long)b >> 32) : 0u;
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) |
+                                            ((unsigned long long)b & 0xffffffffull)));
 }
 
 // x, y, z of record j: AoS records of 1 << qshift bytes (the position is the
@@ -150,10 +164,10 @@ __device__ __forceinline__ double kick_row(const ForceArgs& a, int64_t i, double
 }
 
 // Loads are issued U entries (U / 4 groups of 4 steps) at a time, and the
-// indices of the next U entries are requested before the current ones are
-// computed, so each wavefront keeps up to 2U gathers and U / 4 index loads in
-// flight (the load/compute overlap that software pipelining gives a CPU
-// core).
+// indices of the entries two batches ahead are requested before the current
+// ones are computed, so each wavefront keeps up to 2U gathers and U / 2 index
+// loads in flight (the load/compute overlap that software pipelining gives a
+// CPU core).
 // The forces of one slice of system sid, computed by the calling wavefront
 // (C = 64 / G rows, G lanes per row); returns the lane's shares of the
 // energy, the virial, the pair count and (with a kick) the kinetic energy,
@@ -195,7 +209,8 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
         a.col + sy.col0 + (int64_t)(slice - sy.slice0) * (sy.cap / G) * LJ_WAVE);
     const uint32_t lane_off = (uint32_t)lane * 16u;
     double fx = 0.0, fy = 0.0, fz = 0.0, sA = 0.0, sB = 0.0, sR = 0.0;
-    int cnt = 0;
+    int cnt = 0;       // the lane's pairs outside the loop (the mixed kernels' band pass)
+    int wcnt = 0;      // the wavefront's pairs in the loop (wave-uniform)
 
     // The lane's indices of steps 4 q .. 4 q + 3: one 16-byte load from the
     // slice's group q, clamped into the slice so that every index load is
@@ -212,9 +227,6 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
         return *reinterpret_cast<const int*>(colbase + (uint32_t)((it >> 2) * LJ_WAVE * 16) +
                                              lane_off + (uint32_t)(it & 3) * 4u);
     };
-    v4i jq[NQ];
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) jq[q] = group_at(q);
     // the force constants as values, read once
     const double sig2 = fc.sig2, c24 = fc.c24, c48 = fc.c48;
     const float sig2f = fc.sig2f, c24f = fc.c24f, c48f = fc.c48f;
@@ -227,15 +239,24 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
     uint4 qi4 = make_uint4(0u, 0u, 0u, 0u);
     if constexpr (PREC != LJ_FP64) qi4 = a.q32[ri];
     bool had_amb = false;
+    // FP64: the terms in powers of 1/r^2, sigma^6 and sigma^12 folded into
+    // the constants: fs = (1/r^8) (48 eps sigma^12 / r^6 - 24 eps sigma^6),
+    // and the energy sums over 1/r^6 and 1/r^12 scaled after the loop
+    const double sig6 = sig2 * sig2 * sig2;
+    const double sig12 = sig6 * sig6;
+    const double k48 = c48 * sig12, k24 = c24 * sig6;
     // pair terms of an interacting entry from its r^2 (mixed: FP32 terms);
-    // rr: the pair's distance r for the force-shifted energy (0 if masked)
+    // sr6d: the term whose sum and sum of squares give the energy and virial
+    // (FP64: 1/r^6, mixed: (sigma/r)^6, zero if masked); rr: the pair's
+    // distance r for the force-shifted energy (0 if masked)
     auto pair_terms = [&](double r2, bool m, double& fs, double& sr6d, double& rr) {
         if constexpr (PREC == LJ_FP64) {
-            const double ir2 = m ? recip(r2) : 0.0;
-            const double sr2 = sig2 * ir2;
-            const double sr6 = sr2 * sr2 * sr2;
-            fs = ir2 * (sr6 * fma(c48, sr6, -c24));
-            sr6d = sr6;
+            const double ir2 = keep_or_tiny(m, recip(r2));
+            const double ir4 = ir2 * ir2;
+            const double ir6 = ir4 * ir2;
+            const double ir8 = ir4 * ir4;
+            fs = ir8 * fma(k48, ir6, -k24);
+            sr6d = ir6;
             if constexpr (FS) {
                 const double rd = m ? __builtin_sqrt(r2) : 0.0;
                 fs = fma(-fcut * rd, ir2, fs);     // fs - Fc / r
@@ -262,69 +283,118 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
         ty = (double)(int32_t)(qj.y - qi4.y) * qs1;
         tz = (double)(int32_t)(qj.z - qi4.z) * qs2;
     };
-    for (int it0 = 0; it0 < iters; it0 += U) {
-        double px[U], py[U], pz[U];
-        uint4 qv[U];
-        int jn[U];
+    // The nearest-image correction is needed only by slices whose rows reach
+    // across a periodic face (the list build records which): the others run
+    // the loop without it.
+    const bool img =
+        PREC == LJ_FP64 && __builtin_amdgcn_readfirstlane(a.slice_stats[slice].w) != 0;
+    auto run = [&](auto img_c) {
+        constexpr bool IMG = decltype(img_c)::value;
+        // Index groups in two sets used alternately (even and odd batches): a
+        // batch's set is refilled with the indices two batches ahead as soon as
+        // its gathers are issued (the list streams from HBM), and no register
+        // copies make the refill wait.
+        v4i ja[NQ], jb[NQ];
 #pragma unroll
-        for (int u = 0; u < U; ++u) jn[u] = jq[u >> 2][u & 3];
-        if constexpr (PREC == LJ_FP64) {
-            // the (x, y) record and z of each entry: 24 bytes over 16- and
-            // 8-byte records (the 8 entries a row takes per step span about
-            // half the cache lines of 32-byte records)
+        for (int q = 0; q < NQ; ++q) {
+            ja[q] = group_at(q);
+            jb[q] = group_at(NQ + q);
+        }
+        // one batch of U entries starting at step it0, its indices in jq
+        auto batch = [&](v4i* jq, int it0) {
+            // a batch's loads stay in their place (not hoisted into the previous
+            // batch's arithmetic, which would hold more registers and order its
+            // gathers behind the index refill)
+            __builtin_amdgcn_sched_barrier(0);
+            double px[U], py[U], pz[U];
+            uint4 qv[U];
+            int jn[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) jn[u] = jq[u >> 2][u & 3];
+            if constexpr (PREC == LJ_FP64) {
+                // the (x, y) record and z of each entry: 24 bytes over 16- and
+                // 8-byte records (the 8 entries a row takes per step span about
+                // half the cache lines of 32-byte records)
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const double2 q = *reinterpret_cast<const double2*>(
+                        reinterpret_cast<const char*>(a.xy) + (uint32_t)jn[u] * 16u);
+                    px[u] = q.x;
+                    py[u] = q.y;
+                    pz[u] = *reinterpret_cast<const double*>(
+                        reinterpret_cast<const char*>(a.zz) + (uint32_t)jn[u] * 8u);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) qv[u] = a.q32[jn[u]];
+            }
+            int jc[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) jc[u] = jn[u];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) jq[q] = group_at((it0 + 2 * U) / 4 + q);
+            // keep the next indices' loads issued here, ahead of the arithmetic
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const double2 q = *reinterpret_cast<const double2*>(
-                    reinterpret_cast<const char*>(a.xy) + (uint32_t)jn[u] * 16u);
-                px[u] = q.x;
-                py[u] = q.y;
-                pz[u] = *reinterpret_cast<const double*>(
-                    reinterpret_cast<const char*>(a.zz) + (uint32_t)jn[u] * 8u);
+                // (a step at or past iters is past every row's length as well)
+                const bool valid = (it0 + u) * G < lim;
+                double tx, ty, tz, fs, sr6d, rr = 0.0;
+                bool in, m;
+                if constexpr (PREC == LJ_FP64) {
+                    tx = px[u] - qx;
+                    ty = py[u] - qy;
+                    tz = pz[u] - qz;
+                    if constexpr (IMG) {
+                        tx = fma(-rint(tx * ibx), bx, tx);
+                        ty = fma(-rint(ty * iby), by, ty);
+                        tz = fma(-rint(tz * ibz), bz, tz);
+                    }
+                    const double r2 = r2_rounded(tx, ty, tz);
+                    in = r2 < rc2;
+                    m = valid && in;
+                    pair_terms(r2, m, fs, sr6d, rr);
+                } else {
+                    fixed_disp(qv[u], tx, ty, tz);
+                    const double r2 = r2_rounded(tx, ty, tz);
+                    in = r2 < rc2lo;
+                    m = valid && in;
+                    had_amb = had_amb || (valid && !(r2 < rc2lo) && (r2 < rc2hi));
+                    pair_terms(r2, m, fs, sr6d, rr);
+                }
+                // energy and virial from two sums: sum (sigma/r)^12 and sum (sigma/r)^6
+                // (and sum r for the force-shifted truncation)
+                sA = fma(sr6d, sr6d, sA);
+                sB += sr6d;
+                if constexpr (FS) sR += rr;
+                // (two ballots of plain compares: lane masks the compares already wrote)
+                wcnt += __builtin_popcountll(__builtin_amdgcn_ballot_w64(in) &
+                                             __builtin_amdgcn_ballot_w64(valid));
+                fx = fma(-fs, tx, fx);
+                fy = fma(-fs, ty, fy);
+                fz = fma(-fs, tz, fz);
+                if (HALF && m) acc_add(a.acc, a.n16, jc[u], fs * tx, fs * ty, fs * tz);
             }
-        } else {
-#pragma unroll
-            for (int u = 0; u < U; ++u) qv[u] = a.q32[jn[u]];
+        };
+        // whole pairs of batches, then an odd last batch: the loop's back edge
+        // always comes from the second batch, so its head waits only for the
+        // first set's indices (requested two batches earlier)
+        const int nbatch = (iters + U - 1) / U;
+        int it0 = 0;
+        for (int p = 0; p < (nbatch >> 1); ++p, it0 += 2 * U) {
+            batch(ja, it0);
+            batch(jb, it0 + U);
         }
-        int jc[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) jc[u] = jn[u];
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) jq[q] = group_at((it0 + U) / 4 + q);
-        // keep the next indices' loads issued here, ahead of the arithmetic
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const bool valid = (it0 + u < iters) && ((it0 + u) * G < lim);
-            double tx, ty, tz, fs, sr6d, rr = 0.0;
-            bool m;
-            if constexpr (PREC == LJ_FP64) {
-                tx = px[u] - qx;
-                ty = py[u] - qy;
-                tz = pz[u] - qz;
-                tx = fma(-rint(tx * ibx), bx, tx);
-                ty = fma(-rint(ty * iby), by, ty);
-                tz = fma(-rint(tz * ibz), bz, tz);
-                const double r2 = r2_rounded(tx, ty, tz);
-                m = valid && (r2 < rc2);
-                pair_terms(r2, m, fs, sr6d, rr);
-            } else {
-                fixed_disp(qv[u], tx, ty, tz);
-                const double r2 = r2_rounded(tx, ty, tz);
-                m = valid && (r2 < rc2lo);
-                had_amb = had_amb || (valid && !(r2 < rc2lo) && (r2 < rc2hi));
-                pair_terms(r2, m, fs, sr6d, rr);
-            }
-            // energy and virial from two sums: sum (sigma/r)^12 and sum (sigma/r)^6
-            // (and sum r for the force-shifted truncation)
-            sA = fma(sr6d, sr6d, sA);
-            sB += sr6d;
-            if constexpr (FS) sR += rr;
-            cnt += m ? 1 : 0;
-            fx = fma(-fs, tx, fx);
-            fy = fma(-fs, ty, fy);
-            fz = fma(-fs, tz, fz);
-            if (HALF && m) acc_add(a.acc, a.n16, jc[u], fs * tx, fs * ty, fs * tz);
-        }
+        if (nbatch & 1) batch(ja, it0);
+    };
+    // (the mixed kernels' fixed-point differences wrap by themselves)
+    if constexpr (PREC == LJ_FP64) {
+        if (img)
+            run(std::true_type());
+        else
+            run(std::false_type());
+    } else {
+        run(std::false_type());
     }
     if constexpr (PREC != LJ_FP64) {
         // rare: entries whose fixed-point r^2 fell within the band around rc^2,
@@ -378,14 +448,19 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
             if (a.write_f) store_f<LAYOUT>(a.force, a.n, i, fx, fy, fz);
         }
     }
-    // per lane: 4 eps (A - B) [+ Fc sum r] and 24 eps (2A - B) [- Fc sum r]
+    // per lane: 4 eps (A - B) [+ Fc sum r] and 24 eps (2A - B) [- Fc sum r],
+    // A and B the sums of (sigma/r)^12 and (sigma/r)^6
+    if constexpr (PREC == LJ_FP64) {
+        sA *= sig12;
+        sB *= sig6;
+    }
     e_out = fc.c4 * (sA - sB);
     w_out = fc.c24 * (2.0 * sA - sB);
     if constexpr (FS) {
         e_out = fma(fcut, sR, e_out);
         w_out = fma(-fcut, sR, w_out);
     }
-    c_out = (double)cnt;
+    c_out = (double)(cnt + (lane == 0 ? wcnt : 0));
     k_out = ke;
 }
 

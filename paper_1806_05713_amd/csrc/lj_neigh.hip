@@ -52,7 +52,8 @@ struct NeighArgs {
     int32_t* row_len;
     int32_t* slice_iters;
     int4* slice_stats;     // per slice: longest row before clamping, entries stored,
-                           // candidates tested, unused
+                           // candidates tested, and 1 if a row has entries across a
+                           // periodic face (the force kernel then takes nearest images)
     int32_t* col;
     lj_dev_status* st;     // a row that overflows its capacity raises a flag here
     const int32_t* gate;   // when not NULL, build only if *gate != 0 (decided on the device)
@@ -415,7 +416,7 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_neigh(NeighArgs a) {
     }
     if ((lane % SL) == 0) {
         a.slice_iters[slice] = iters;
-        a.slice_stats[slice] = make_int4(over, tot, ntest, 0);
+        a.slice_stats[slice] = make_int4(over, tot, ntest, 1);   // images not tracked here
     }
 }
 
@@ -555,6 +556,7 @@ __global__ __launch_bounds__(LJ_BLOCK, 7) void k_neigh_rows(NeighArgs a) {
 
     int keep_len = 0, keep_self = 0, keep_atom = 0;   // lane r: row r of the wavefront
     int sl_mx = 0, sl_over = 0, sl_tot = 0, sl_tests = 0;
+    bool sl_img = false;
 
     // the atoms of all the wavefront's rows (one load) and their cell
     // geometry, one lane per row, kept in LDS
@@ -798,6 +800,8 @@ __global__ __launch_bounds__(LJ_BLOCK, 7) void k_neigh_rows(NeighArgs a) {
             sl_over = max(sl_over, cnt);
             sl_tot += len;
             sl_tests += T;
+            // a dimension scanned whole takes nearest images in the walk
+            sl_img = sl_img || row_img || (ANYFULL && (stn.fullx || stn.fully || stn.fullz));
             if ((rr + 1) % C == 0) {
                 // the slice is complete: pad its rows with their own atom
                 const int iters = (sl_mx + G - 1) / G;
@@ -813,9 +817,10 @@ __global__ __launch_bounds__(LJ_BLOCK, 7) void k_neigh_rows(NeighArgs a) {
                 if (lane == 0) {
                     const int64_t slice = slice_first + rr / C;
                     a.slice_iters[slice] = iters;
-                    a.slice_stats[slice] = make_int4(sl_over, sl_tot, sl_tests, 0);
+                    a.slice_stats[slice] = make_int4(sl_over, sl_tot, sl_tests, sl_img ? 1 : 0);
                 }
                 sl_mx = sl_over = sl_tot = sl_tests = 0;
+                sl_img = false;
             }
         }
     }
