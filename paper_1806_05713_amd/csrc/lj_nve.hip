@@ -17,7 +17,8 @@
 // its own) and so the same trajectory bit for bit:
 //   separate (half lists, and the displacement rule): the kick that ends
 //     step k and the drift that opens step k + 1 are one streaming kernel
-//     (k_kick_drift); a chain of steps ends with a kick of its own (k_kick);
+//     (k_drift in its kick-and-drift mode); a chain of steps ends with a
+//     kick of its own (k_kick);
 //   folded into the force pass (full lists at a fixed cadence; the momentum
 //     update of Alg. 1): the force kernel kicks each row's atom as soon as
 //     its force is summed, twice inside a rebuild cycle (ending this step and
