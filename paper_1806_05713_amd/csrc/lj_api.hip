@@ -350,7 +350,7 @@ lj_status alloc_rows(lj_list* l, hipStream_t stream) {
         (st = dmalloc(&l->row_len, rows)) || (st = dmalloc(&l->slice_iters, l->nslices)) ||
         (st = dmalloc(&l->slice_stats, l->nslices)) || (st = dmalloc(&l->stats, l->nsys)) ||
         (st = dmalloc(&l->dsys, l->nsys)) || (st = dmalloc(&l->fc, l->nsys)) ||
-        (st = dmalloc(&l->xy, l->n)) || (st = dmalloc(&l->zz, l->n)))
+        (st = dmalloc(&l->xy, rows)) || (st = dmalloc(&l->zz, rows)))
         return st;
     if (l->kind == LJ_LIST_HALF) {
         // the half list's spread force accumulator, zero between force calls
@@ -703,7 +703,7 @@ extern "C" lj_status lj_build_neighbors_batch(lj_ctx* ctx, const double* pos, in
 // use, outside any graph capture.
 lj_status lj_list_ensure_q32(lj_list* l) {
     if (l->q32) return LJ_OK;
-    return dmalloc(&l->q32, l->n);
+    return dmalloc(&l->q32, l->nslices * (LJ_WAVE / l->lanes));
 }
 
 lj_status lj_list_ensure_cells(lj_ctx* ctx, lj_list* l) {

@@ -170,11 +170,14 @@ __global__ __launch_bounds__(1024) void k_force_reduce(const double4* __restrict
     }
 }
 
-// The copies the force kernel gathers from, in cell-sorted rank order (the
-// list's entries are ranks, so the rows' neighbours sit close together in
-// memory whatever the caller's atom order): one thread per row of the list;
-// the thread of a system's k-th row reads the position of that row's atom
-// and writes the system's k-th rank.
+// The copies the force kernel gathers from, one record per row of the list
+// (rows are in cell-sorted rank order, so the rows' neighbours sit close
+// together in memory whatever the caller's atom order; a system's rank j is
+// its row j + slice0 C - atom0, a per-system offset the force kernel adds to
+// its base pointers): the thread of row r reads the position of the row's
+// atom and writes record r.  Rows past a system's atoms hold atom 0 and are
+// never gathered, so every thread stores and none waits for the system's
+// descriptor.
 //   FP64: (x, y) 16-byte records and z;
 //   mixed: each coordinate as a 32-bit fraction of its box length,
 //     u = rint(x 2^32 / L) mod 2^32.  A wrapping 32-bit difference u_j - u_i
@@ -185,7 +188,6 @@ __global__ __launch_bounds__(1024) void k_force_reduce(const double4* __restrict
 template <int LAYOUT, int PREC>
 __global__ __launch_bounds__(LJ_BLOCK) void k_gather_copy(const double* __restrict__ pos,
                                                           int64_t n, uint32_t qshift,
-                                                          const lj_sys* sys,
                                                           const int32_t* slice_sys, int C,
                                                           const int32_t* __restrict__ row_atom,
                                                           const lj_fconst* fc,
@@ -193,12 +195,6 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_gather_copy(const double* __restri
                                                           double* __restrict__ zz,
                                                           uint4* __restrict__ q32) {
     const int64_t r = blockIdx.x * (int64_t)LJ_BLOCK + threadIdx.x;
-    const int sid = __builtin_amdgcn_readfirstlane(
-        slice_sys[(blockIdx.x * (int64_t)LJ_BLOCK) / C]);
-    const lj_sys& sy = sys[sid];
-    const int64_t t = r - sy.slice0 * C;
-    if (t >= sy.n) return;
-    const int64_t rank = sy.atom0 + t;
     const int64_t i = row_atom[r];
     double x, y, z;
     if (LAYOUT == LJ_AOS4) {
@@ -213,11 +209,13 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_gather_copy(const double* __restri
         z = pos[2 * n + i];
     }
     if (PREC == LJ_FP64) {
-        xy[rank] = make_double2(x, y);
-        zz[rank] = z;
+        xy[r] = make_double2(x, y);
+        zz[r] = z;
     } else {
+        const int sid = __builtin_amdgcn_readfirstlane(
+            slice_sys[(blockIdx.x * (int64_t)LJ_BLOCK) / C]);
         const lj_fconst& f = fc[sid];
-        q32[rank] = make_uint4(lj_fix32(x, f.qinv[0]), lj_fix32(y, f.qinv[1]),
+        q32[r] = make_uint4(lj_fix32(x, f.qinv[0]), lj_fix32(y, f.qinv[1]),
                                lj_fix32(z, f.qinv[2]), 0u);
     }
 }
@@ -453,7 +451,7 @@ lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int preci
             const dim3 qgrid((unsigned)(l->nslices * C / LJ_BLOCK));
 #define LJ_COPY(L, P)                                                                      \
     hipLaunchKernelGGL((k_gather_copy<L, P>), qgrid, dim3(LJ_BLOCK), 0, ctx->stream, pos, \
-                       l->n, a.qshift, (const lj_sys*)l->dsys, (const int32_t*)l->slice_sys, C, \
+                       l->n, a.qshift, (const int32_t*)l->slice_sys, C,                    \
                        (const int32_t*)l->row_atom, fc, l->xy, l->zz, l->q32)
             if (tl == LJ_AOS4) {
                 if (precision == LJ_FP64) LJ_COPY(LJ_AOS4, LJ_FP64); else LJ_COPY(LJ_AOS4, LJ_MIXED);

@@ -31,9 +31,10 @@ struct ForceArgs {
                              // by rank
     int64_t n16;
     uint4* q32;              // mixed: fixed-point positions (x, y, z as fractions of the
-                             // box) in cell-sorted rank order
-    const double2* xy;       // FP64: the positions in cell-sorted rank order, split into
-    const double* zz;        // (x, y) records and z: one 16-byte and one 8-byte gather
+                             // box), one per row
+    const double2* xy;       // FP64: the positions, one per row, split into (x, y)
+    const double* zz;        // records and z: one 16-byte and one 8-byte gather
+                             // (the row of rank j of a system is j + slice0 C - atom0)
     const int32_t* halt;     // device status flags: the kernel does nothing once an
                              // error flag is raised (NULL: never)
     uint32_t qshift;         // AoS record stride as a shift: 5 (32-byte records) or 6
@@ -196,11 +197,16 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
     const double ibx = sy.inv_box[0], iby = sy.inv_box[1], ibz = sy.inv_box[2];
     const double rc2 = fc.rc2;
     double qx, qy, qz;
+    // the copies' records of this system, indexed by rank (a uniform offset)
+    const int64_t rows_off = sy.slice0 * C - sy.atom0;
+    const double2* __restrict__ xys = a.xy + rows_off;
+    const double* __restrict__ zzs = a.zz + rows_off;
+    const uint4* __restrict__ q32s = a.q32 + rows_off;
     if constexpr (PREC == LJ_FP64) {
-        const double2 q = a.xy[ri];
+        const double2 q = xys[ri];
         qx = q.x;
         qy = q.y;
-        qz = a.zz[ri];
+        qz = zzs[ri];
     } else {
         gather_q<LAYOUT>(a.pos, a.n, a.qshift, i, qx, qy, qz);
     }
@@ -237,7 +243,7 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
     // mixed: the row atom's fixed-point record; whether the lane met an entry
     // whose r^2 lies in the quantisation band of rc^2 (decided after the loop)
     uint4 qi4 = make_uint4(0u, 0u, 0u, 0u);
-    if constexpr (PREC != LJ_FP64) qi4 = a.q32[ri];
+    if constexpr (PREC != LJ_FP64) qi4 = q32s[ri];
     bool had_amb = false;
     // FP64: the terms in powers of 1/r^2, sigma^6 and sigma^12 folded into
     // the constants: fs = (1/r^8) (48 eps sigma^12 / r^6 - 24 eps sigma^6),
@@ -318,15 +324,15 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const double2 q = *reinterpret_cast<const double2*>(
-                        reinterpret_cast<const char*>(a.xy) + (uint32_t)jn[u] * 16u);
+                        reinterpret_cast<const char*>(xys) + (uint32_t)jn[u] * 16u);
                     px[u] = q.x;
                     py[u] = q.y;
                     pz[u] = *reinterpret_cast<const double*>(
-                        reinterpret_cast<const char*>(a.zz) + (uint32_t)jn[u] * 8u);
+                        reinterpret_cast<const char*>(zzs) + (uint32_t)jn[u] * 8u);
                 }
             } else {
 #pragma unroll
-                for (int u = 0; u < U; ++u) qv[u] = a.q32[jn[u]];
+                for (int u = 0; u < U; ++u) qv[u] = q32s[jn[u]];
             }
             int jc[U];
 #pragma unroll
@@ -403,7 +409,7 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
             for (int it = 0; it < iters && it * G < lim; ++it) {
                 const int j = idx_at(it);
                 double tx, ty, tz;
-                fixed_disp(a.q32[j], tx, ty, tz);
+                fixed_disp(q32s[j], tx, ty, tz);
                 const double r2 = r2_rounded(tx, ty, tz);
                 if (r2 < rc2lo || !(r2 < rc2hi)) continue;
                 // the atom of rank j: the row of that rank

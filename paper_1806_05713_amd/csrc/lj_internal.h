@@ -180,10 +180,10 @@ struct lj_list {
     bool fc_valid;
     lj_cells* cells;               // owned cell structure for in-place rebuilds (lazy)
     double* acc;                   // half list: spread force accumulator, zero between calls
-    uint4* q32;                    // mixed precision: fixed-point positions (n records by
-                                   // cell-sorted rank, lazy)
-    double2* xy;                   // FP64 forces gather from this copy of the positions by
-    double* zz;                    // cell-sorted rank: (x, y) 16-byte records and z
+    uint4* q32;                    // mixed precision: fixed-point positions (one record per
+                                   // row, lazy)
+    double2* xy;                   // FP64 forces gather from this copy of the positions, one
+    double* zz;                    // per row: (x, y) 16-byte records and z
 };
 
 // ---------------------------------------------------------------- errors
