@@ -223,10 +223,11 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_gather_copy(const double* __restri
 // Wavefronts per SIMD the compiler must fit (1: no constraint).  The plain
 // full-list loop (4 entries per batch) fits in 80 registers without spilling,
 // which lets 6 wavefronts share a SIMD instead of 5 (4% faster in FP64, 6% in
-// mixed precision at 131k atoms); the other forms would spill at that bound.
+// mixed precision at 131k atoms); the force-shifted loop fits 5 in 96 (4
+// unbounded).  The half-list and 8-entry forms would spill at such bounds.
 template <bool HALF, int U, bool FS>
 constexpr int force_waves() {
-    return (!HALF && U == 4 && !FS) ? 6 : 1;
+    return (HALF || U != 4) ? 1 : (FS ? 5 : 6);
 }
 
 // One wavefront per slice; a block's four slices belong to one system
