@@ -265,12 +265,14 @@ def bench_batch512(steps: int = 100, warmup: int = 10, tune: bool = False) -> di
     return res
 
 
-def accuracy_lj500k(steps: int = 10000, rebuild_every: int = 10):
+def accuracy_lj500k(steps: int = 10000, rebuild_every: int = 0):
     """Mixed-precision accuracy run on the 500,000-atom fluid (rho = 1.0,
     T = 0.7, rc = 3.0, skin = 0.3, dt = 0.005), FP64 and mixed trajectories
     from the same initial state.
 
-    Per step of the mixed trajectory, the FP64 kernel re-evaluates the forces
+    rebuild_every = 0 (the default) rebuilds the list when some atom has moved
+    more than skin/2 since the last build, so both trajectories use exact
+    lists.  Per step of the mixed trajectory, the FP64 kernel re-evaluates the forces
     on the same positions with the same list; the error is
     max_i |F_mixed_i - F_fp64_i| / max_i |F_fp64_i| (norms per component).
     Step 0 is the perfect lattice, where every force vanishes by symmetry and
@@ -323,7 +325,9 @@ def accuracy_lj500k(steps: int = 10000, rebuild_every: int = 10):
                  "E_end": float(log[-1, 0] + log[-1, 1]),
                  "max_abs_rel_dE": float(np.max(np.abs((log[:, 0] + log[:, 1]) /
                                                        (log[0, 0] + log[0, 1]) - 1.0))),
-                 "T_end": float(2.0 * log[-1, 1] / (3 * s.n - 3))}
+                 "T_end": float(2.0 * log[-1, 1] / (3 * s.n - 3)),
+                 "rebuilds": int(log[1:, 5].sum()),
+                 "max_displacement_between_builds": float(log[:, 3].max())}
             if prec == lj.LJ_MIXED:
                 d = err.cpu().numpy()
                 fm = fmax.cpu().numpy()
@@ -338,7 +342,9 @@ def accuracy_lj500k(steps: int = 10000, rebuild_every: int = 10):
                           "max_abs_f64_min_over_steps": float(fm[1:].min()),
                           "pe_rel_err_max": float(np.max(np.abs(pe_mixed / pe_f64 - 1.0)))})
             res[prec_name] = r
+    rule = (f"list rebuilt every {rebuild_every} steps" if rebuild_every else
+            "list rebuilt when an atom has moved more than skin/2 since the last build")
     return {"workload": "mixed-precision accuracy run: 500,000 atoms (50^3 FCC x4), rho=1.0, "
-                        "Maxwell T=0.7, rc=3.0, skin=0.3, dt=0.005, list rebuilt every "
-                        f"{rebuild_every} steps, {steps} velocity-Verlet steps, full list",
+                        f"Maxwell T=0.7, rc=3.0, skin=0.3, dt=0.005, {rule}, {steps} "
+                        "velocity-Verlet steps, full list",
             "atoms": s.n, "steps": steps, **res}
