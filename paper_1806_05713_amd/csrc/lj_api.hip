@@ -529,6 +529,7 @@ extern "C" lj_status lj_create(int device, void* stream, lj_ctx** out) {
     ctx->device = device;
     ctx->stream = (hipStream_t)stream;
     ctx->prof_on = false;
+    ctx->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     for (int k = 0; k < LJ_TUNE_N; ++k) ctx->tune[k] = 0;
     lj_status st = dmalloc(&ctx->st, 1);
     if (st) {

@@ -124,6 +124,7 @@ struct lj_ctx {
     bool prof_on;
     std::vector<lj_prof_rec> prof;
     int32_t tune[LJ_TUNE_N];       // tuning knobs (lj_tune_set)
+    int cus;                       // compute units of the device
 };
 
 // Records HIP events around a launch on the context's stream while the

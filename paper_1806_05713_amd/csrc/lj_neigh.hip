@@ -494,11 +494,14 @@ __device__ __forceinline__ double dword_pair(unsigned int lo, unsigned int hi) {
 
 // At least 7 wavefronts per SIMD (up to 72 VGPRs): at 8 (64 VGPRs) the set-up
 // spills to scratch, which costs more than the eighth wavefront gains.
-template <int G, bool HALF, bool ANYFULL>
+// RWMIN: at least this many rows per wavefront (8 or 16; whole slices in any
+// case).  Large systems take 16: half the blocks, which matters when a
+// launch gated off by the displacement rule still dispatches every block.
+template <int G, bool HALF, bool ANYFULL, int RWMIN>
 __global__ __launch_bounds__(LJ_BLOCK, 7) void k_neigh_rows(NeighArgs a) {
     if (gated_off(a.gate)) return;
     constexpr int C = LJ_WAVE / G;          // rows per slice of the layout
-    constexpr int RW = C > 8 ? C : 8;       // rows per wavefront: whole slices
+    constexpr int RW = C > RWMIN ? C : RWMIN;   // rows per wavefront: whole slices
     __shared__ RowTable tables[LJ_WAVES_PER_BLOCK];
     __shared__ double4 shift[27];     // image shift of each code (the block's system)
     __shared__ float4 shift32[27];    // the same rounded to FP32
@@ -906,10 +909,10 @@ lj_status launch_g(lj_ctx* ctx, const NeighArgs& a, bool half, bool anyfull) {
     return LJ_OK;
 }
 
-template <int G>
-lj_status launch_rows(lj_ctx* ctx, const NeighArgs& a, bool half, bool anyfull) {
+template <int G, int RWMIN>
+lj_status launch_rows_rw(lj_ctx* ctx, const NeighArgs& a, bool half, bool anyfull) {
     constexpr int C = LJ_WAVE / G;
-    constexpr int RW = C > 8 ? C : 8;
+    constexpr int RW = C > RWMIN ? C : RWMIN;
     const int64_t rows = a.nslices * C;
     const int64_t waves = (rows + RW - 1) / RW;
     const int64_t blocks = (waves + LJ_WAVES_PER_BLOCK - 1) / LJ_WAVES_PER_BLOCK;
@@ -917,17 +920,28 @@ lj_status launch_rows(lj_ctx* ctx, const NeighArgs& a, bool half, bool anyfull) 
     lj_prof_scope prof(ctx, LJ_PROF_NEIGH);
     if (half) {
         if (anyfull)
-            hipLaunchKernelGGL((k_neigh_rows<G, true, true>), grid, block, 0, ctx->stream, a);
+            hipLaunchKernelGGL((k_neigh_rows<G, true, true, RWMIN>), grid, block, 0, ctx->stream, a);
         else
-            hipLaunchKernelGGL((k_neigh_rows<G, true, false>), grid, block, 0, ctx->stream, a);
+            hipLaunchKernelGGL((k_neigh_rows<G, true, false, RWMIN>), grid, block, 0, ctx->stream, a);
     } else {
         if (anyfull)
-            hipLaunchKernelGGL((k_neigh_rows<G, false, true>), grid, block, 0, ctx->stream, a);
+            hipLaunchKernelGGL((k_neigh_rows<G, false, true, RWMIN>), grid, block, 0, ctx->stream, a);
         else
-            hipLaunchKernelGGL((k_neigh_rows<G, false, false>), grid, block, 0, ctx->stream, a);
+            hipLaunchKernelGGL((k_neigh_rows<G, false, false, RWMIN>), grid, block, 0, ctx->stream,
+                               a);
     }
     LJ_HIP(hipGetLastError());
     return LJ_OK;
+}
+
+// 16 rows per wavefront once the list has rows for more than four rounds of
+// resident blocks at 16 (7 wavefronts per SIMD), else 8.
+template <int G>
+lj_status launch_rows(lj_ctx* ctx, const NeighArgs& a, bool half, bool anyfull) {
+    const int64_t rows = a.nslices * (LJ_WAVE / G);
+    const int64_t resident_rows16 = (int64_t)ctx->cus * 4 * 7 * 16;
+    if (rows >= 4 * resident_rows16) return launch_rows_rw<G, 16>(ctx, a, half, anyfull);
+    return launch_rows_rw<G, 8>(ctx, a, half, anyfull);
 }
 
 }  // namespace
