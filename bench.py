@@ -265,8 +265,11 @@ def main():
     # choice for this device and workload shape, else the library's defaults
     tkey = autotune.system_key(s.n, 1.0, s.rc + s.skin, kind, lj.LJ_FP64)
     if args.tune:
+        # tuned for the whole step (list build + force evaluation): the list
+        # layout serves both, and the shape that gives the force kernel alone
+        # its last few percent (4 lanes per row) slows the build by a third
         shape = autotune.best_config(ctx, pos, s.box, s.rc, s.skin, kind, lj.LJ_FP64, 1.0,
-                                     objective="force_us", retune=True,
+                                     objective="step_us", retune=True,
                                      space={"lanes": (4, 8, 16), "build_lanes": (64,),
                                             "batch": (2, 4, 8), "cell_div": (2,)},
                                      log=lambda m: print(f"[tune] {m}", file=sys.stderr))
