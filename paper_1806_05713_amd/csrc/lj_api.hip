@@ -166,6 +166,7 @@ void list_release(lj_list* l) {
     dfree(l->slice_iters);
     dfree(l->slice_stats);
     dfree(l->acc);
+    dfree(l->hwin);
     dfree(l->q32);
     dfree(l->xy);
     dfree(l->zz);
@@ -355,7 +356,8 @@ lj_status alloc_rows(lj_list* l, hipStream_t stream) {
     if (l->kind == LJ_LIST_HALF) {
         // the half list's spread force accumulator, zero between force calls
         const int64_t words = 3 * 16 * ((l->n + 15) / 16);
-        if ((st = dmalloc(&l->acc, words)) ||
+        if ((st = dmalloc(&l->hwin, lj_force_blocks(l->nslices) * LJ_HWIN_REC)) ||
+            (st = dmalloc(&l->acc, words)) ||
             (st = lj_launch_zero(stream, l->acc, words * (int64_t)sizeof(double))))
             return st;
     }

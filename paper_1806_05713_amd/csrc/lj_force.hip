@@ -241,8 +241,106 @@ __attribute__((amdgpu_waves_per_eu(force_waves<HALF, U, FS>()))) void k_force(Fo
         (int)blk * LJ_WAVES_PER_BLOCK + (threadIdx.x >> 6));
     const int sid = __builtin_amdgcn_readfirstlane(a.slice_sys[blk * LJ_WAVES_PER_BLOCK]);
     double e, w, c, k;
-    slice_forces<G, HALF, LAYOUT, PREC, U, FS>(a, slice, sid, e, w, c, k);
+    if constexpr (HALF) {
+        // the block's window (its chunk table and LDS sums), then the
+        // slices, then the window's sums added to the accumulator once
+        __shared__ int4 htab4[LJ_HWIN_TABLE / 16];
+        __shared__ double hacc[3 * LJ_HWIN_MAX * LJ_HWIN_CHUNK];
+        __shared__ int hoff[LJ_HWIN_MAX];
+        signed char* htab = reinterpret_cast<signed char*>(htab4);
+        constexpr int C = LJ_WAVE / G;
+        constexpr int HS = LJ_HWIN_MAX * LJ_HWIN_CHUNK;
+        const lj_sys& sy = a.sys[sid];
+        const int c0 = (int)((blk * LJ_WAVES_PER_BLOCK * C - sy.slice0 * C) >> LJ_HWIN_SHIFT);
+        const int nch = (int)((sy.n + LJ_HWIN_CHUNK - 1) >> LJ_HWIN_SHIFT);
+        for (int t = threadIdx.x; t < LJ_HWIN_TABLE / 16; t += LJ_BLOCK)
+            htab4[t] = make_int4(-1, -1, -1, -1);
+        for (int t = threadIdx.x; t < 3 * HS; t += LJ_BLOCK) hacc[t] = 0.0;
+        const int32_t* rec = a.hwin + blk * LJ_HWIN_REC;
+        const int cnt = __builtin_amdgcn_readfirstlane(rec[0]);
+        __syncthreads();
+        if ((int)threadIdx.x < cnt) {
+            const int off = rec[1 + threadIdx.x];
+            hoff[threadIdx.x] = off;
+            htab[off + LJ_HWIN_TABLE / 2] = (signed char)threadIdx.x;
+        }
+        __syncthreads();
+        slice_forces<G, HALF, LAYOUT, PREC, U, FS>(a, slice, sid, e, w, c, k, htab, hacc, c0);
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt * LJ_HWIN_CHUNK; t += LJ_BLOCK) {
+            int ch = c0 + hoff[t >> LJ_HWIN_SHIFT];
+            ch += ch < 0 ? nch : (ch >= nch ? -nch : 0);
+            const int64_t rel = (int64_t)ch * LJ_HWIN_CHUNK + (t & (LJ_HWIN_CHUNK - 1));
+            const double x = hacc[t], y = hacc[HS + t], z = hacc[2 * HS + t];
+            if (rel < sy.n && (x != 0.0 || y != 0.0 || z != 0.0))
+                acc_add(a.acc, a.n16, sy.atom0 + rel, x, y, z);
+        }
+    } else {
+        slice_forces<G, HALF, LAYOUT, PREC, U, FS>(a, slice, sid, e, w, c, k, nullptr, nullptr,
+                                                   0);
+    }
     block_partials(a, blk, e, w, c, k);
+}
+
+// The window of each half-list force block (one thread block per force
+// block): the chunks of LJ_HWIN_CHUNK ranks named by any slot of its slices
+// (entries and the rows' own padding), marked in an LDS table of offsets,
+// then numbered in offset order; the first LJ_HWIN_MAX are the window.
+__global__ __launch_bounds__(LJ_BLOCK) void k_half_windows(const int32_t* __restrict__ col,
+                                                           const lj_sys* sys,
+                                                           const int32_t* slice_sys,
+                                                           const int32_t* slice_iters, int C,
+                                                           int G, int32_t* __restrict__ hwin,
+                                                           const int32_t* gate) {
+    if (gate && __builtin_nontemporal_load(gate) == 0) return;
+    __shared__ int4 mark4[LJ_HWIN_TABLE / 16];
+    __shared__ int wsum[LJ_WAVES_PER_BLOCK];
+    unsigned char* mark = reinterpret_cast<unsigned char*>(mark4);
+    const int tid = threadIdx.x, lane = tid & (LJ_WAVE - 1), wave = tid >> 6;
+    for (int k = tid; k < LJ_HWIN_TABLE / 16; k += LJ_BLOCK) mark4[k] = make_int4(0, 0, 0, 0);
+    const int64_t blk = blockIdx.x;
+    const int64_t slice0 = blk * LJ_WAVES_PER_BLOCK;
+    const int sid = __builtin_amdgcn_readfirstlane(slice_sys[slice0]);
+    const lj_sys& sy = sys[sid];
+    const int c0 = (int)((slice0 * C - sy.slice0 * C) >> LJ_HWIN_SHIFT);
+    const int nch = (int)((sy.n + LJ_HWIN_CHUNK - 1) >> LJ_HWIN_SHIFT);
+    __syncthreads();
+    for (int w = 0; w < LJ_WAVES_PER_BLOCK; ++w) {
+        const int64_t t = slice0 + w;
+        const int64_t nslots = (int64_t)((slice_iters[t] + 3) & ~3) * LJ_WAVE;
+        const int32_t* base = col + sy.col0 + (t - sy.slice0) * (int64_t)(sy.cap / G) * LJ_WAVE;
+        for (int64_t k = tid; k < nslots; k += LJ_BLOCK) {
+            const int ti = lj_hwin_offset(base[k] - (int)sy.atom0, c0, nch) + LJ_HWIN_TABLE / 2;
+            if (ti >= 0 && ti < LJ_HWIN_TABLE) mark[ti] = 1;
+        }
+    }
+    __syncthreads();
+    // number the marked offsets in order: thread t owns table bytes
+    // [t * 64, t * 64 + 64), a block-wide exclusive sum gives its first number
+    constexpr int PER = LJ_HWIN_TABLE / LJ_BLOCK;
+    const unsigned char* own = mark + tid * PER;
+    int cnt = 0;
+    for (int k = 0; k < PER; ++k) cnt += own[k];
+    int incl = cnt;
+    for (int d = 1; d < LJ_WAVE; d <<= 1) {
+        const int v = __shfl_up(incl, d, LJ_WAVE);
+        if (lane >= d) incl += v;
+    }
+    if (lane == LJ_WAVE - 1) wsum[wave] = incl;
+    __syncthreads();
+    int before = incl - cnt, total = 0;
+    for (int w = 0; w < LJ_WAVES_PER_BLOCK; ++w) {
+        if (w < wave) before += wsum[w];
+        total += wsum[w];
+    }
+    int32_t* rec = hwin + blk * LJ_HWIN_REC;
+    for (int k = 0; k < PER; ++k) {
+        if (own[k]) {
+            if (before < LJ_HWIN_MAX) rec[1 + before] = tid * PER + k - LJ_HWIN_TABLE / 2;
+            ++before;
+        }
+    }
+    if (tid == 0) rec[0] = total < LJ_HWIN_MAX ? total : LJ_HWIN_MAX;
 }
 
 // Half list: the forces from the accumulator (by rank), which is cleared for
@@ -357,6 +455,18 @@ int64_t lj_force_partials(const lj_list* l) {
     return lj_force_blocks(l->nslices) + (split > 1 ? (int64_t)l->nsys * split : 0);
 }
 
+lj_status lj_launch_half_windows(lj_ctx* ctx, lj_list* l, const int32_t* gate) {
+    if (l->kind != LJ_LIST_HALF || !l->hwin) return LJ_OK;
+    lj_prof_scope prof(ctx, LJ_PROF_NEIGH);
+    hipLaunchKernelGGL(k_half_windows, dim3((unsigned)lj_force_blocks(l->nslices)),
+                       dim3(LJ_BLOCK), 0, ctx->stream, (const int32_t*)l->col,
+                       (const lj_sys*)l->dsys, (const int32_t*)l->slice_sys,
+                       (const int32_t*)l->slice_iters, LJ_WAVE / l->lanes, l->lanes, l->hwin,
+                       gate);
+    LJ_HIP(hipGetLastError());
+    return LJ_OK;
+}
+
 lj_fconst lj_make_fconst(double eps, double sigma, double rc, const double box[3], int trunc) {
     lj_fconst f = {};
     f.rc2 = rc * rc;
@@ -430,6 +540,7 @@ lj_status lj_launch_forces(lj_ctx* ctx, const double* pos, int layout, int preci
     a.col = l->col;
     a.partials = partials;
     a.acc = l->acc;
+    a.hwin = l->hwin;
     a.q32 = l->q32;
     a.xy = l->xy;
     a.zz = l->zz;

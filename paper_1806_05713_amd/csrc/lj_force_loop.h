@@ -29,6 +29,7 @@ struct ForceArgs {
     double* partials;        // 4 doubles per (logical) block
     double* acc;             // half list: spread force accumulator (3 x 16 n16 doubles),
                              // by rank
+    const int32_t* hwin;     // half list: the force blocks' windows
     int64_t n16;
     uint4* q32;              // mixed: fixed-point positions (x, y, z as fractions of the
                              // box), one per row
@@ -178,7 +179,8 @@ __device__ __forceinline__ double kick_row(const ForceArgs& a, int64_t i, double
 template <int G, bool HALF, int LAYOUT, int PREC, int U, bool FS>
 __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int sid,
                                              double& e_out, double& w_out, double& c_out,
-                                             double& k_out) {
+                                             double& k_out, const signed char* htab,
+                                             double* hacc, int hc0) {
     constexpr int C = LJ_WAVE / G;
     const int lane = threadIdx.x & (LJ_WAVE - 1);
     const lj_sys& sy = a.sys[sid];
@@ -293,6 +295,30 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
             sr6d = (double)sr6;
         }
     };
+    // half lists: the j share of a pair (rank j) goes to the block's window in
+    // LDS when j's chunk is in it, else straight to the accumulator
+    const int hnch = (int)((sy.n + LJ_HWIN_CHUNK - 1) >> LJ_HWIN_SHIFT);
+    // (the window slot of rank j, or -1: looked up as soon as j is known, so
+    // that the LDS read overlaps the pair arithmetic)
+    auto j_slot = [&](int j) -> int {
+        const int ti = lj_hwin_offset(j - (int)sy.atom0, hc0, hnch) + LJ_HWIN_TABLE / 2;
+        return (ti >= 0 && ti < LJ_HWIN_TABLE) ? (int)htab[ti] : -1;
+    };
+    auto j_put = [&](int j, int slot, double x, double y, double z) {
+        const int rel = j - (int)sy.atom0;
+        if (slot >= 0) {
+            // (workgroup scope: LDS atomics, kept apart from the global ones)
+            double* p = hacc + slot * LJ_HWIN_CHUNK + (rel & (LJ_HWIN_CHUNK - 1));
+            __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(p + LJ_HWIN_MAX * LJ_HWIN_CHUNK, y, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(p + 2 * LJ_HWIN_MAX * LJ_HWIN_CHUNK, z, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        } else {
+            acc_add(a.acc, a.n16, j, x, y, z);
+        }
+    };
+    auto j_add = [&](int j, double x, double y, double z) { j_put(j, j_slot(j), x, y, z); };
     auto fixed_disp = [&](const uint4& qj, double& tx, double& ty, double& tz) {
         // nearest-image displacement from the wrapping fixed-point
         // difference: an exact integer times an exact unit, one rounding
@@ -345,9 +371,12 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
 #pragma unroll
                 for (int u = 0; u < U; ++u) qv[u] = q32s[jn[u]];
             }
-            int jc[U];
+            int jc[U], js[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) jc[u] = jn[u];
+            for (int u = 0; u < U; ++u) {
+                jc[u] = jn[u];
+                if constexpr (HALF) js[u] = j_slot(jn[u]);
+            }
 #pragma unroll
             for (int q = 0; q < NQ; ++q) jq[q] = group_at((it0 + 2 * U) / 4 + q);
             // keep the next indices' loads issued here, ahead of the arithmetic
@@ -390,7 +419,9 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
                 fx = fma(-fs, tx, fx);
                 fy = fma(-fs, ty, fy);
                 fz = fma(-fs, tz, fz);
-                if (HALF && m) acc_add(a.acc, a.n16, jc[u], fs * tx, fs * ty, fs * tz);
+                if constexpr (HALF) {
+                    if (m) j_put(jc[u], js[u], fs * tx, fs * ty, fs * tz);
+                }
             }
         };
         // whole pairs of batches, then an odd last batch: the loop's back edge
@@ -443,7 +474,7 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
                 fx = fma(-fs, tx, fx);
                 fy = fma(-fs, ty, fy);
                 fz = fma(-fs, tz, fz);
-                if (HALF) acc_add(a.acc, a.n16, j, fs * tx, fs * ty, fs * tz);
+                if (HALF) j_add(j, fs * tx, fs * ty, fs * tz);
             }
         }
     }
@@ -457,7 +488,7 @@ __device__ __forceinline__ void slice_forces(const ForceArgs& a, int slice, int 
     double ke = 0.0;
     if (g == 0 && row_ok) {
         if (HALF) {
-            acc_add(a.acc, a.n16, ri, fx, fy, fz);
+            j_add(ri, fx, fy, fz);
         } else if (a.kick == LJ_KICK_NONE) {
             store_f<LAYOUT>(a.force, a.n, i, fx, fy, fz);
         } else {

@@ -181,6 +181,8 @@ struct lj_list {
     bool fc_valid;
     lj_cells* cells;               // owned cell structure for in-place rebuilds (lazy)
     double* acc;                   // half list: spread force accumulator, zero between calls
+    int32_t* hwin;                 // half list: each force block's window of rank chunks
+                                   // (count, then up to LJ_HWIN_MAX chunk offsets)
     uint4* q32;                    // mixed precision: fixed-point positions (one record per
                                    // row, lazy)
     double2* xy;                   // FP64 forces gather from this copy of the positions, one
@@ -220,6 +222,27 @@ lj_status lj_launch_list_stats(hipStream_t s, lj_list* l);
 int lj_build_lanes(const lj_ctx* ctx, int lanes);
 // forces (lj_force.hip): per-system energy, virial, pair count
 int64_t lj_force_blocks(int64_t nslices);
+
+// Half lists: a force block sums the j contributions of its entries in LDS
+// for the partners in its window, the set of chunks of LJ_HWIN_CHUNK
+// consecutive ranks its entries name (at most LJ_HWIN_MAX chunks: those of
+// the lowest offsets when a block names more), and adds each window record
+// to the global accumulator once; partners outside the window are added
+// directly.  A chunk is named by its offset from the chunk of the block's
+// first row, taken modulo the system's chunks into (-nch/2, nch/2], and
+// looked up in a table of LJ_HWIN_TABLE offsets.
+#define LJ_HWIN_SHIFT 4
+#define LJ_HWIN_CHUNK (1 << LJ_HWIN_SHIFT)
+#define LJ_HWIN_MAX 96
+#define LJ_HWIN_TABLE 16384
+#define LJ_HWIN_REC (1 + LJ_HWIN_MAX)   // int32 per block in lj_list::hwin
+__device__ __forceinline__ int lj_hwin_offset(int rel, int c0, int nch) {
+    int off = (rel >> LJ_HWIN_SHIFT) - c0;
+    off += off > nch / 2 ? -nch : (off <= -((nch + 1) / 2) ? nch : 0);
+    return off;
+}
+// Window of the half list's force blocks, after each build (gated like it).
+lj_status lj_launch_half_windows(lj_ctx* ctx, lj_list* l, const int32_t* gate);
 // Reduction levels of the force kernel's block partials: the number of
 // first-level spans per system (1: a single level), and the partial records
 // (double4) the context must hold for list l.

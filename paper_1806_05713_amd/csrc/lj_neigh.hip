@@ -994,6 +994,7 @@ lj_status lj_launch_neighbors(lj_ctx* ctx, const lj_cells* c, lj_list* l, bool s
     }
 #undef LJ_GB
     if (st) return st;
+    if ((st = lj_launch_half_windows(ctx, l, gate))) return st;
     if (!stats) {
         l->stats_stale = true;
         return LJ_OK;
