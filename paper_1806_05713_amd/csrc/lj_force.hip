@@ -317,10 +317,19 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_half_windows(const int32_t* __rest
     __syncthreads();
     // number the marked offsets in order: thread t owns table bytes
     // [t * 64, t * 64 + 64), a block-wide exclusive sum gives its first number
+    // (bytes are 0 or 1, so a 32-bit word's count is its bytes' sum)
     constexpr int PER = LJ_HWIN_TABLE / LJ_BLOCK;
-    const unsigned char* own = mark + tid * PER;
+    constexpr int PER4 = PER / 16;
+    int4 wv[PER4];
     int cnt = 0;
-    for (int k = 0; k < PER; ++k) cnt += own[k];
+#pragma unroll
+    for (int q = 0; q < PER4; ++q) {
+        wv[q] = mark4[tid * PER4 + q];
+        cnt += (int)(((unsigned)wv[q].x * 0x01010101u) >> 24) +
+               (int)(((unsigned)wv[q].y * 0x01010101u) >> 24) +
+               (int)(((unsigned)wv[q].z * 0x01010101u) >> 24) +
+               (int)(((unsigned)wv[q].w * 0x01010101u) >> 24);
+    }
     int incl = cnt;
     for (int d = 1; d < LJ_WAVE; d <<= 1) {
         const int v = __shfl_up(incl, d, LJ_WAVE);
@@ -334,10 +343,18 @@ __global__ __launch_bounds__(LJ_BLOCK) void k_half_windows(const int32_t* __rest
         total += wsum[w];
     }
     int32_t* rec = hwin + blk * LJ_HWIN_REC;
-    for (int k = 0; k < PER; ++k) {
-        if (own[k]) {
-            if (before < LJ_HWIN_MAX) rec[1 + before] = tid * PER + k - LJ_HWIN_TABLE / 2;
-            ++before;
+#pragma unroll
+    for (int q = 0; q < PER4; ++q) {
+        const unsigned wq[4] = {(unsigned)wv[q].x, (unsigned)wv[q].y, (unsigned)wv[q].z,
+                                (unsigned)wv[q].w};
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            for (unsigned bits = wq[c]; bits != 0u; bits &= bits - 1u) {
+                const int byte = __builtin_ctz(bits) >> 3;   // the lowest marked byte
+                if (before < LJ_HWIN_MAX)
+                    rec[1 + before] = tid * PER + q * 16 + c * 4 + byte - LJ_HWIN_TABLE / 2;
+                ++before;
+            }
         }
     }
     if (tid == 0) rec[0] = total < LJ_HWIN_MAX ? total : LJ_HWIN_MAX;
